@@ -1,0 +1,173 @@
+/*
+ * rms.h -- C ABI of an MI355X (gfx950) Monte Carlo diffusion walker in 3d
+ * voxelized label volumes, after Lee, Fieremans & Novikov, "Realistic
+ * Microstructure Simulator (RMS)", arXiv 2012.06478.
+ *
+ * Units throughout: micrometres (um), milliseconds (ms), um^2/ms for
+ * diffusivities, um/ms for permeabilities, ms/um^2 for b values.
+ *
+ * Conventions for every entry point:
+ *   - returns RMS_OK (0) or a negative RMS_E_* code; rms_last_error() then
+ *     describes the failure (per calling thread);
+ *   - pointers are host pointers unless stated otherwise; the library copies
+ *     what it needs and never keeps or frees caller memory;
+ *   - no exception crosses the ABI;
+ *   - results are deterministic given the substrate, parameters, seed,
+ *     walker count, step count, protocol and precision: they do not depend on
+ *     the stream, on concurrent calls or on the server's mix of requests.
+ */
+#ifndef RMS_H
+#define RMS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define RMS_ABI_VERSION 1
+
+/* Error codes. */
+#define RMS_OK 0
+#define RMS_E_INVALID_ARG (-1)         /* malformed argument (message says which) */
+#define RMS_E_LABEL_RANGE (-2)         /* a voxel label >= n_labels */
+#define RMS_E_STEP_TOO_LARGE (-3)      /* max step length >= voxel size (section 2.1.1) */
+#define RMS_E_PROB_TOO_LARGE (-4)      /* a permeation probability > 0.5 (Table 1: P << 1) */
+#define RMS_E_UNBALANCED_WAVEFORM (-5) /* |sum_i G_i| > 1e-9 sum_i |G_i| for a shape */
+#define RMS_E_OOM (-6)                 /* device or host allocation failed */
+#define RMS_E_DEVICE (-7)              /* a HIP runtime call failed */
+#define RMS_E_BUSY (-8)                /* server: request cannot be admitted now */
+#define RMS_E_TIMEOUT (-9)             /* server: wait timed out */
+
+/* Precision forms of rms_run. */
+#define RMS_FP64 0  /* double-precision walk and reductions */
+#define RMS_MIXED 1 /* int32 voxel + fp32 offset walk, fp64 reductions */
+
+/* Size limits. */
+#define RMS_MAX_SHAPES 4     /* gradient waveform shapes per run */
+#define RMS_MAX_SIGNALS 960  /* n_shapes * n_b * n_dirs per run */
+#define RMS_MAX_LABELS 4096  /* compartment labels per substrate */
+
+/* Per-walker dump record (doubles), in this order:
+ *   0-2  displacement x, y, z (um, unwrapped)
+ *   3    R = sum_c t_c / T2_c (so alpha = exp(-R))
+ *   4    label at the end
+ *   5-7  voxel index x, y, z at the end
+ *   8-10 offset inside that voxel at the end (voxel lengths, in [0, 1])
+ *   11   label at the start
+ *   12   face events (face reached: pass, permeation or reflection)
+ *   13   membrane hits (faces between different labels)
+ *   14   permeations
+ *   15.. phase vector Phi_s = dt sum_i G_s[i] (x_i - x_0) (3 per shape, um ms)
+ */
+#define RMS_DUMP_FIXED 15
+#define RMS_DUMP_WIDTH(n_shapes) (RMS_DUMP_FIXED + 3 * (n_shapes))
+
+/* Opaque, immutable, device-resident substrate: the label volume (section
+ * 2.1.1: the voxelized geometry is its own lookup table of compartment
+ * labels) plus default tissue parameters.  Safe to share between concurrent
+ * runs and the server once created. */
+typedef struct rms_substrate rms_substrate;
+
+/* Tissue parameters of one run (overrides the substrate defaults).
+ *   D      [n_labels] intrinsic diffusivity D0 per label (um^2/ms), > 0 for
+ *          every label that is not dead (section 2.1.3, Eq. step-size);
+ *   kappa  [n_labels * n_labels] permeability per label pair (um/ms),
+ *          row-major, symmetric, >= 0; the diagonal is ignored; NULL means
+ *          every membrane is impermeable (section 2.1.3, Eq.
+ *          perm-prob-general);
+ *   T2     [n_labels] transverse relaxation time per label (ms), > 0,
+ *          INFINITY for none; NULL means no relaxation (section 2.1.4, Eq.
+ *          wt-relax). */
+typedef struct {
+    int n_labels;
+    const double* D;
+    const double* kappa;
+    const double* T2;
+} rms_params;
+
+/* Results of one run.  The caller allocates every array it wants filled and
+ * sets the pointer (NULL = not wanted); the library fills them.
+ *   signal      [n_shapes][n_b][n_dirs][2] (re, im) of
+ *               S = <alpha exp(-i phi)> / <alpha> (section 2.3, Eq. signal)
+ *   m2          alpha-weighted <dx_i dx_j> / <alpha>, order xx xy xz yy yz zz
+ *   m4          alpha-weighted <dx_i dx_j dx_k dx_l> / <alpha>, i<=j<=k<=l in
+ *               lexicographic order (xxxx xxxy xxxz xxyy xxyz xxzz xyyy xyyz
+ *               xyzz xzzz yyyy yyyz yyzz yzzz zzzz)
+ *   D_dir       [n_dirs] (g.M2.g) / (2 t), t = n_steps dt (section 2.3)
+ *   K_dir       [n_dirs] (M4:g^4) / (g.M2.g)^2 - 3 (section 2.3, with both
+ *               moments divided by <alpha>)
+ *   b_disc      [n_shapes] b value of each shape at unit scale; each shape is
+ *               scaled by sqrt(b / b_disc) so that its discrete b equals b
+ *   walker_dump [n_walkers][RMS_DUMP_WIDTH(n_shapes)] per-walker records */
+typedef struct {
+    double* signal;
+    double m2[6];
+    double m4[15];
+    double* D_dir;
+    double* K_dir;
+    double sum_alpha;
+    double* b_disc;
+    int64_t n_face_events;
+    int64_t n_membrane_hits;
+    int64_t n_permeations;
+    double max_perm_prob;       /* largest permeation probability in the run */
+    double max_step_over_voxel; /* largest ds / voxel size in the run */
+    double wall_s;              /* host wall time of the call */
+    double kernel_ms;           /* walk kernel time, HIP events on the run's stream */
+    double* walker_dump;
+} rms_result;
+
+/* ABI version (RMS_ABI_VERSION of the built library). */
+int rms_abi_version(void);
+
+/* Description of the last failure on the calling thread ("" if none). */
+const char* rms_last_error(void);
+
+/* Build a device-resident substrate (sections 2.1.1 and 2.2 item 1).
+ *   labels      host array of nx*ny*nz labels, x fastest then y then z,
+ *               uint8 (label_bytes = 1) or uint16 (label_bytes = 2); copied;
+ *   dims        {nx, ny, nz}, each >= 1, product < 2^31; the volume is
+ *               periodic in all three axes;
+ *   voxel_um    isotropic voxel size l_p (um), > 0;
+ *   n_labels    number of labels, 1..RMS_MAX_LABELS; every voxel < n_labels;
+ *   D, kappa, T2  default tissue parameters (see rms_params);
+ *   dead        [n_labels] or NULL: nonzero marks a label no walker starts in
+ *               or enters (section 2.2, item 1);
+ *   out         receives the handle.
+ * The substrate lives on the HIP device current at the call. */
+int rms_create_substrate(const void* labels, int label_bytes, const int64_t dims[3],
+                         double voxel_um, int n_labels, const double* D, const double* kappa,
+                         const double* T2, const uint8_t* dead, rms_substrate** out);
+
+/* Free a substrate (NULL is a no-op).  No run may be using it. */
+void rms_destroy_substrate(rms_substrate* sub);
+
+/* Simulate n_walkers independent walkers for n_steps steps of dt_ms each
+ * (section 2.2, items 1-5) and reduce their signals and moments (section
+ * 2.3).
+ *   sub          substrate; params overrides its tissue parameters (NULL =
+ *                substrate defaults; n_labels must match);
+ *   seed         64-bit key of the counter-based random streams: walker w's
+ *                trajectory depends only on (seed, w, substrate, params, dt);
+ *   n_walkers    >= 1; n_steps in [0, 2^32 - 2]; dt_ms > 0;
+ *   n_shapes     0..RMS_MAX_SHAPES gradient shapes; waveform is
+ *                [n_shapes][n_steps], sample i applies during step i+1, each
+ *                shape balanced (sum of samples ~ 0);
+ *   dirs         [n_dirs][3] gradient directions (normalized here);
+ *   bvals        [n_b] b values >= 0 (b > 0 needs a nonzero shape);
+ *   precision    RMS_FP64 or RMS_MIXED;
+ *   hip_stream   hipStream_t to run on (NULL = the null stream);
+ *   out          results (see rms_result).
+ * Blocks until the results are in host memory. */
+int rms_run(const rms_substrate* sub, const rms_params* params, uint64_t seed, int64_t n_walkers,
+            int64_t n_steps, double dt_ms, int n_shapes, const double* waveform, int n_dirs,
+            const double* dirs, int n_b, const double* bvals, int precision, void* hip_stream,
+            rms_result* out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RMS_H */

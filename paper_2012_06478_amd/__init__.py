@@ -1,0 +1,228 @@
+"""MI355X Monte Carlo diffusion walker (after Lee, Fieremans & Novikov, "Realistic
+Microstructure Simulator", arXiv 2012.06478): Python binding of ``librms.so``.
+
+This module only marshals arguments to the C ABI of ``include/rms.h``; every
+step of the walk runs in the library's HIP kernels.  The functions carry the
+C names: ``rms_create_substrate``, ``rms_destroy_substrate``, ``rms_run``,
+``rms_abi_version``, ``rms_last_error``.  Importing works without a GPU (the
+library loads); calls that touch the device need one.  If the library has not
+been built, loading fails loudly: there is no other implementation behind
+these names.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librms.so")
+
+RMS_OK = 0
+RMS_FP64 = 0
+RMS_MIXED = 1
+RMS_MAX_SHAPES = 4
+RMS_MAX_SIGNALS = 960
+RMS_MAX_LABELS = 4096
+RMS_DUMP_FIXED = 15
+ERROR_NAMES = {
+    -1: "RMS_E_INVALID_ARG", -2: "RMS_E_LABEL_RANGE", -3: "RMS_E_STEP_TOO_LARGE",
+    -4: "RMS_E_PROB_TOO_LARGE", -5: "RMS_E_UNBALANCED_WAVEFORM", -6: "RMS_E_OOM",
+    -7: "RMS_E_DEVICE", -8: "RMS_E_BUSY", -9: "RMS_E_TIMEOUT",
+}
+DUMP_FIELDS = ["dx", "dy", "dz", "R", "label", "ix", "iy", "iz", "ox", "oy", "oz",
+               "label0", "n_face", "n_hit", "n_perm"]
+
+
+class RmsError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{ERROR_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class _Params(C.Structure):
+    _fields_ = [("n_labels", C.c_int), ("D", C.POINTER(C.c_double)),
+                ("kappa", C.POINTER(C.c_double)), ("T2", C.POINTER(C.c_double))]
+
+
+class _Result(C.Structure):
+    _fields_ = [("signal", C.POINTER(C.c_double)), ("m2", C.c_double * 6),
+                ("m4", C.c_double * 15), ("D_dir", C.POINTER(C.c_double)),
+                ("K_dir", C.POINTER(C.c_double)), ("sum_alpha", C.c_double),
+                ("b_disc", C.POINTER(C.c_double)), ("n_face_events", C.c_int64),
+                ("n_membrane_hits", C.c_int64), ("n_permeations", C.c_int64),
+                ("max_perm_prob", C.c_double), ("max_step_over_voxel", C.c_double),
+                ("wall_s", C.c_double), ("kernel_ms", C.c_double),
+                ("walker_dump", C.POINTER(C.c_double))]
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    try:  # share torch's HIP runtime (same SONAME) so its streams are valid here
+        import torch  # noqa: F401
+    except ImportError:
+        pass
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() "
+                          "(hipcc --offload-arch=gfx950)")
+    lib = C.CDLL(LIB_PATH)
+    dp, i64p, u8p = C.POINTER(C.c_double), C.POINTER(C.c_int64), C.POINTER(C.c_uint8)
+    lib.rms_abi_version.restype = C.c_int
+    lib.rms_last_error.restype = C.c_char_p
+    lib.rms_create_substrate.argtypes = [C.c_void_p, C.c_int, i64p, C.c_double, C.c_int, dp, dp,
+                                         dp, u8p, C.POINTER(C.c_void_p)]
+    lib.rms_create_substrate.restype = C.c_int
+    lib.rms_destroy_substrate.argtypes = [C.c_void_p]
+    lib.rms_destroy_substrate.restype = None
+    lib.rms_run.argtypes = [C.c_void_p, C.POINTER(_Params), C.c_uint64, C.c_int64, C.c_int64,
+                            C.c_double, C.c_int, dp, C.c_int, dp, C.c_int, dp, C.c_int,
+                            C.c_void_p, C.POINTER(_Result)]
+    lib.rms_run.restype = C.c_int
+    _lib = lib
+    return lib
+
+
+def exported_symbols() -> list[str]:
+    """Names the library exports through the C ABI (for load checks)."""
+    lib = _load()
+    names = ["rms_abi_version", "rms_last_error", "rms_create_substrate",
+             "rms_destroy_substrate", "rms_run"]
+    return [n for n in names if hasattr(lib, n)]
+
+
+def rms_abi_version() -> int:
+    return _load().rms_abi_version()
+
+
+def rms_last_error() -> str:
+    return _load().rms_last_error().decode()
+
+
+def _check(rc: int):
+    if rc != RMS_OK:
+        raise RmsError(rc, rms_last_error())
+
+
+def _dptr(a):
+    return None if a is None else a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+class Substrate:
+    """Handle of a device-resident substrate (``rms_substrate*``)."""
+
+    def __init__(self, handle, labels_shape, n_labels, voxel_um):
+        self.handle = handle
+        self.shape = labels_shape
+        self.n_labels = n_labels
+        self.voxel_um = voxel_um
+
+    def close(self):
+        if self.handle:
+            _load().rms_destroy_substrate(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def rms_create_substrate(labels, voxel_um, D, kappa=None, T2=None, dead=None) -> Substrate:
+    """``labels``: [nz, ny, nx] uint8/uint16 array (x fastest); D [n]; kappa
+    [n, n] or None; T2 [n] or None; dead [n] bool or None."""
+    lib = _load()
+    lab = np.ascontiguousarray(labels)
+    if lab.ndim != 3 or lab.dtype not in (np.uint8, np.uint16):
+        raise TypeError("labels must be a 3d uint8 or uint16 array")
+    dims = np.array(lab.shape[::-1], np.int64)
+    Dv = np.ascontiguousarray(D, np.float64)
+    n = Dv.size
+    kap = None if kappa is None else np.ascontiguousarray(kappa, np.float64).reshape(n * n)
+    t2 = None if T2 is None else np.ascontiguousarray(T2, np.float64)
+    dd = None if dead is None else np.ascontiguousarray(dead, np.uint8)
+    h = C.c_void_p()
+    rc = lib.rms_create_substrate(lab.ctypes.data, lab.dtype.itemsize,
+                                  dims.ctypes.data_as(C.POINTER(C.c_int64)), float(voxel_um), n,
+                                  _dptr(Dv), _dptr(kap), _dptr(t2),
+                                  None if dd is None else dd.ctypes.data_as(C.POINTER(C.c_uint8)),
+                                  C.byref(h))
+    _check(rc)
+    return Substrate(h, lab.shape, n, voxel_um)
+
+
+def rms_destroy_substrate(sub: Substrate) -> None:
+    sub.close()
+
+
+def _stream_handle(stream):
+    if stream is None:
+        return None
+    if isinstance(stream, int):
+        return stream
+    return int(stream.cuda_stream)  # torch.cuda.Stream (HIP stream on ROCm)
+
+
+def rms_run(sub: Substrate, *, seed, n_walkers, n_steps, dt, waveform=None, dirs=None,
+            bvals=None, precision=RMS_FP64, params=None, stream=None, dump=False) -> dict:
+    """Run the walk; returns a dict of numpy results (see ``include/rms.h``).
+
+    ``params``: optional dict with ``D``, ``kappa``, ``T2`` overriding the
+    substrate's tissue parameters.  ``stream``: a torch.cuda.Stream or a raw
+    hipStream_t (int); None runs on the null stream."""
+    lib = _load()
+    W = (np.zeros((0, n_steps)) if waveform is None
+         else np.ascontiguousarray(np.atleast_2d(waveform), np.float64))
+    ns = W.shape[0]
+    g = (np.zeros((0, 3)) if dirs is None
+         else np.ascontiguousarray(dirs, np.float64).reshape(-1, 3))
+    b = np.zeros(0) if bvals is None else np.ascontiguousarray(bvals, np.float64)
+    nd, nb = g.shape[0], b.size
+    keep = []
+    pp = None
+    if params is not None:
+        Dv = np.ascontiguousarray(params["D"], np.float64)
+        kap = params.get("kappa")
+        kap = None if kap is None else np.ascontiguousarray(kap, np.float64).reshape(-1)
+        t2 = params.get("T2")
+        t2 = None if t2 is None else np.ascontiguousarray(t2, np.float64)
+        keep += [Dv, kap, t2]
+        pp = _Params(Dv.size, _dptr(Dv), _dptr(kap), _dptr(t2))
+    sig = np.zeros(max(ns * nb * nd, 1) * 2)
+    Dd = np.zeros(max(nd, 1))
+    Kd = np.zeros(max(nd, 1))
+    bd = np.zeros(max(ns, 1))
+    wd = np.zeros((int(n_walkers), RMS_DUMP_FIXED + 3 * ns)) if dump else None
+    res = _Result()
+    res.signal = _dptr(sig)
+    res.D_dir = _dptr(Dd)
+    res.K_dir = _dptr(Kd)
+    res.b_disc = _dptr(bd)
+    res.walker_dump = _dptr(wd) if wd is not None else None
+    rc = lib.rms_run(sub.handle, None if pp is None else C.byref(pp), int(seed) & (2**64 - 1),
+                     int(n_walkers), int(n_steps), float(dt), ns, _dptr(W), nd, _dptr(g), nb,
+                     _dptr(b), int(precision), _stream_handle(stream), C.byref(res))
+    _check(rc)
+    out = dict(
+        signal=(sig[0::2] + 1j * sig[1::2])[: ns * nb * nd].reshape(ns, nb, nd),
+        m2=np.array(res.m2[:]), m4=np.array(res.m4[:]), D=Dd[:nd].copy(), K=Kd[:nd].copy(),
+        sum_alpha=res.sum_alpha, b_disc=bd[:ns].copy(), n_face_events=res.n_face_events,
+        n_membrane_hits=res.n_membrane_hits, n_permeations=res.n_permeations,
+        max_perm_prob=res.max_perm_prob, max_step_over_voxel=res.max_step_over_voxel,
+        wall_s=res.wall_s, kernel_ms=res.kernel_ms,
+    )
+    if wd is not None:
+        out["dump"] = wd
+        out["phase"] = wd[:, RMS_DUMP_FIXED:].reshape(int(n_walkers), ns, 3)
+    return out
+
+
+__all__ = ["rms_abi_version", "rms_last_error", "rms_create_substrate", "rms_destroy_substrate",
+           "rms_run", "Substrate", "RmsError", "RMS_FP64", "RMS_MIXED", "exported_symbols",
+           "DUMP_FIELDS"]

@@ -1,0 +1,63 @@
+// Internal interface between the host side of the library (rms_api.cpp) and
+// the gfx950 kernels (rms_walk.hip, rms_reduce.hip).  Not installed.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace rms {
+
+constexpr int kBlock = 256;  // threads per block of every kernel here
+constexpr int kDumpFixed = 15;
+
+// Everything the walk kernel reads.  All pointers are device pointers.
+struct WalkPlan {
+    const void* labels;  // nx*ny*nz labels, x fastest (uint8 or uint16)
+    int label_bytes;
+    int nx, ny, nz;
+    const uint32_t* allowed;  // ascending linear indices of non-dead voxels, or null (all)
+    uint32_t n_allowed;
+    int n_labels;
+    const double* sigma;    // [n_labels] step length per label, voxel units
+    const double* inv_t2;   // [n_labels] 1/T2 (0 for none)
+    const uint32_t* thr;    // [n_labels^2] permeation thresholds: word < thr permeates
+    const float* sigma_f;   // fp32 copies for the mixed form
+    const float* inv_t2_f;
+    uint64_t seed;
+    int64_t n_walkers;
+    int64_t n_steps;
+    double dt;
+    double voxel_um;
+    int n_shapes;
+    const double* gdt;   // [n_shapes][n_steps] dt * G_s[i]
+    const float* gdt_f;  // fp32 copy for the mixed form
+    double* wstate;      // [n_walkers][kDumpFixed + 3 n_shapes] per-walker results
+};
+
+// Everything the reduction kernels read.
+struct ReducePlan {
+    const double* wstate;
+    int64_t n_walkers;
+    int width;   // doubles per walker record
+    int n_shapes;
+    int n_sig;   // n_shapes * n_b * n_dirs
+    const double* kg;      // [n_sig][3] k_{s,b} * unit direction, um^-1 ms^-1
+    const int* sig_shape;  // [n_sig] shape of each signal
+    int n_acc;             // 25 + 2 n_sig accumulated values per walker
+    int n_blocks;          // blocks of the contribution kernel
+    double* partial;       // [n_acc][n_blocks]
+    double* sums;          // [n_acc]
+    int n_dirs;
+    const double* dirs;    // [n_dirs][3] unit directions
+    double t_ms;           // n_steps * dt
+    double* result;        // [25 + 2 n_sig + 2 n_dirs]
+};
+
+constexpr int kAccFixed = 25;  // alpha, 6 M2, 15 M4, 3 counters
+
+hipError_t launch_walk_fp64(const WalkPlan& p, hipStream_t s);
+hipError_t launch_walk_mixed(const WalkPlan& p, hipStream_t s);
+hipError_t launch_reduce(const ReducePlan& p, hipStream_t s);
+
+}  // namespace rms

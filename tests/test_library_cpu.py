@@ -1,0 +1,55 @@
+"""CPU-side checks of the C-ABI library: it loads, exports every symbol the
+header declares, and rejects bad substrates before touching a device."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2012_06478_amd as rms
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    text = open(os.path.join(ROOT, "include", "rms.h")).read()
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(rms_\w+)\s*\(", text, re.M)))
+
+
+def test_header_symbols_exported():
+    names = _declared_functions()
+    assert "rms_run" in names and "rms_create_substrate" in names
+    lib = rms._load()
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_abi_version_matches_header():
+    text = open(os.path.join(ROOT, "include", "rms.h")).read()
+    v = int(re.search(r"#define RMS_ABI_VERSION (\d+)", text).group(1))
+    assert rms.rms_abi_version() == v
+
+
+def test_label_range_rejected_before_device():
+    lab = np.zeros((4, 4, 4), np.uint8)
+    lab[0, 0, 0] = 3
+    with pytest.raises(rms.RmsError) as e:
+        rms.rms_create_substrate(lab, 0.1, [2.0, 2.0])
+    assert e.value.code == -2
+    assert "label 3" in rms.rms_last_error()
+
+
+@pytest.mark.parametrize("bad", [dict(voxel_um=0.0), dict(D=[])])
+def test_bad_substrate_arguments(bad):
+    kw = dict(labels=np.zeros((2, 2, 2), np.uint8), voxel_um=0.1, D=[2.0])
+    kw.update(bad)
+    with pytest.raises(rms.RmsError) as e:
+        rms.rms_create_substrate(**kw)
+    assert e.value.code == -1
+
+
+def test_header_limits_match_binding():
+    text = open(os.path.join(ROOT, "include", "rms.h")).read()
+    for name in ("RMS_MAX_SHAPES", "RMS_MAX_SIGNALS", "RMS_MAX_LABELS", "RMS_DUMP_FIXED"):
+        v = int(re.search(rf"#define {name} (\d+)", text).group(1))
+        assert getattr(rms, name) == v
