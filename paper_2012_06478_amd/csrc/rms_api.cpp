@@ -402,6 +402,7 @@ int rms_run(const rms_substrate* sub, const rms_params* params, uint64_t seed, i
     wp.gdt = d_gdt;
     wp.gdt_f = d_gdt_f;
     wp.wstate = d_wstate;
+    wp.state = nullptr;
 
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     RMS_HIP(hipEventCreate(&ev0));
@@ -415,7 +416,7 @@ int rms_run(const rms_substrate* sub, const rms_params* params, uint64_t seed, i
     RMS_HIP(hipEventCreate(&ev1));
     eguard.b = ev1;
     RMS_HIP(hipEventRecord(ev0, stream));
-    e = precision == RMS_FP64 ? rms::launch_walk_fp64(wp, stream) : rms::launch_walk_mixed(wp, stream);
+    e = rms::launch_walk(wp, precision, stream);
     if (e != hipSuccess) return hip_fail("walk kernel launch", e);
     RMS_HIP(hipEventRecord(ev1, stream));
 

@@ -1,0 +1,448 @@
+// Device-side walkers for gfx950: the per-walker state and one step of the
+// Monte Carlo walk of Lee, Fieremans & Novikov (arXiv 2012.06478), in two
+// precision forms.  Included by the kernel translation unit only.
+//
+// Method:
+//   - a step has fixed length ds = sqrt(6 D dt) and a uniform random direction
+//     (section 2.2, items 2-3; section 2.1.3, Eq. step-size);
+//   - with ds below the voxel size a step meets at most one face per axis, so
+//     at most three (section 2.1.1 and the corner-reflector figure); a face
+//     between equal labels is transparent, one between different labels is a
+//     membrane: permeate with the probability of Eq. (perm-prob-general), else
+//     reflect specularly (section 2.1.3, section 2.2 items 3-4);
+//   - the phase accumulates g . (x - x0) after every step and the T2 weight the
+//     time spent in each compartment (section 2.3, Eq. signal; section 2.1.4
+//     Eq. wt-relax).
+//
+// Face walk.  Reflection flips one component of the direction and passing
+// changes only the voxel index, so the path length at which a step reaches
+// each axis' face is fixed at the start of the step: e_a = gap_a / |v_a|.  A
+// step sorts the three e_a once and visits them in order while they lie inside
+// the path budget; only a permeation into a label with another step length
+// moves that budget (the remaining share of the step's duration is kept).  The
+// end point on each axis then follows in closed form.
+//
+// Random numbers: Philox4x32-10 (Salmon et al., SC'11) keyed by the 64-bit
+// seed with counter (index, substream, walker_lo, walker_hi): substream 0
+// block j gives the directions of steps 2j+1 (words 0, 1) and 2j+2 (words 2,
+// 3); substream 1 block i-1 the membrane words of step i, in order of use;
+// substream 2 blocks 0 and 1 the start.  A walker's trajectory therefore
+// depends only on (seed, walker index, step index), and a walk can stop after
+// any step and resume from its stored state with identical results.
+//
+// Mixed form: the position is an exact int32 voxel index plus an fp32 offset,
+// so a coordinate keeps the same absolute precision anywhere in the volume
+// (the point of taking voxel membership from the integer part, section
+// 2.1.1).  Directions use the hardware sine and cosine (argument in
+// revolutions, so 2 pi u needs no range reduction); face distances, end points
+// and budgets are fp32; the displacement is the exact count of voxels crossed
+// plus the fp32 offset change; the phase and R are Neumaier-compensated fp32
+// sums.  Permeation uses the same 32-bit thresholds and words as the fp64
+// form.
+#pragma once
+
+#include "rms_internal.h"
+
+namespace rms {
+namespace dev {
+
+__device__ __forceinline__ uint4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2,
+                                               uint32_t c3, uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t p0 = static_cast<uint64_t>(0xD2511F53u) * c0;
+        const uint64_t p1 = static_cast<uint64_t>(0xCD9E8D57u) * c2;
+        const uint32_t n0 = static_cast<uint32_t>(p1 >> 32) ^ c1 ^ k0;
+        const uint32_t n2 = static_cast<uint32_t>(p0 >> 32) ^ c3 ^ k1;
+        c1 = static_cast<uint32_t>(p1);
+        c3 = static_cast<uint32_t>(p0);
+        c0 = n0;
+        c2 = n2;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return make_uint4(c0, c1, c2, c3);
+}
+
+// (w + 1/2) 2^-32, exact in double
+__device__ __forceinline__ double unit_open(uint32_t w) {
+    return fma(static_cast<double>(w), 0x1p-32, 0x1p-33);
+}
+
+__device__ __forceinline__ int wrap_step(int c, int d, int n) {
+    c += d;
+    c = c < 0 ? c + n : c;
+    return c >= n ? c - n : c;
+}
+
+// Neumaier compensated accumulation: s + c carries the sum of every x added.
+__device__ __forceinline__ void nsum(float& s, float& c, float x) {
+    const float t = s + x;
+    c += fabsf(s) >= fabsf(x) ? (s - t) + x : (x - t) + s;
+    s = t;
+}
+
+// Walker identity and Philox key.
+struct Ids {
+    uint32_t wlo, whi, k0, k1;
+};
+
+// Start (section 2.2, item 1): uniform over the voxels that are not dead, then
+// uniform inside the voxel.
+struct Start {
+    int ix, iy, iz;
+    uint32_t lin;
+    uint32_t wox, woy, woz;  // offset words
+};
+
+__device__ __forceinline__ Start draw_start(const WalkPlan& p, const Ids& id) {
+    const uint4 b0 = philox4x32_10(0u, 2u, id.wlo, id.whi, id.k0, id.k1);
+    const uint4 b1 = philox4x32_10(1u, 2u, id.wlo, id.whi, id.k0, id.k1);
+    const uint64_t r64 = (static_cast<uint64_t>(b0.y) << 32) | b0.x;
+    const uint32_t rank =
+        static_cast<uint32_t>(__umul64hi(r64, static_cast<uint64_t>(p.n_allowed)));
+    Start s;
+    s.lin = p.allowed ? p.allowed[rank] : rank;
+    const uint32_t nxy = static_cast<uint32_t>(p.nx) * static_cast<uint32_t>(p.ny);
+    s.iz = static_cast<int>(s.lin / nxy);
+    const uint32_t rem = s.lin - static_cast<uint32_t>(s.iz) * nxy;
+    s.iy = static_cast<int>(rem / static_cast<uint32_t>(p.nx));
+    s.ix = static_cast<int>(rem - static_cast<uint32_t>(s.iy) * static_cast<uint32_t>(p.nx));
+    s.wox = b0.z;
+    s.woy = b0.w;
+    s.woz = b1.x;
+    return s;
+}
+
+// ---------------------------------------------------------------------------
+// Double-precision form.
+// ---------------------------------------------------------------------------
+template <typename LabelT, int NS>
+struct WalkerF64 {
+    static constexpr int kShapes = NS > 0 ? NS : 1;
+    int ix, iy, iz, l, l0;
+    uint32_t nface, nhit, nperm;
+    double o[3];
+    double sig, it2;
+    double d[3];  // displacement, voxel units
+    double R;
+    double ph[kShapes][3];  // phase vector, voxel units x ms
+
+    __device__ __forceinline__ void init(const WalkPlan& p, const LabelT* __restrict__ lab,
+                                         const Ids& id) {
+        const Start s = draw_start(p, id);
+        ix = s.ix;
+        iy = s.iy;
+        iz = s.iz;
+        o[0] = unit_open(s.wox);
+        o[1] = unit_open(s.woy);
+        o[2] = unit_open(s.woz);
+        l = l0 = lab[s.lin];
+        sig = p.sigma[l];
+        it2 = p.inv_t2[l];
+        d[0] = d[1] = d[2] = 0.0;
+        R = 0.0;
+#pragma unroll
+        for (int q = 0; q < kShapes; ++q) ph[q][0] = ph[q][1] = ph[q][2] = 0.0;
+        nface = nhit = nperm = 0;
+    }
+
+    // One step (index i0 = i - 1) with direction words wa, wb.
+    __device__ __forceinline__ void step(const WalkPlan& p, const LabelT* __restrict__ lab,
+                                         uint32_t i0, uint32_t wa, uint32_t wb, const Ids& id) {
+        const double u1 = unit_open(wa);
+        const double u2 = unit_open(wb);
+        double sn, cs;
+        sincospi(2.0 * u2, &sn, &cs);
+        const double rho = 2.0 * sqrt(u1 * (1.0 - u1));
+        const double v[3] = {rho * cs, rho * sn, 1.0 - 2.0 * u1};
+
+        // path length to the face each axis moves toward
+        double e[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const double av = fabs(v[a]);
+            const double gap = fmax(v[a] > 0.0 ? 1.0 - o[a] : o[a], 0.0);
+            e[a] = av > 0.0 ? gap / av : INFINITY;
+        }
+        // stable sort of (e, axis): ties keep x < y < z
+        double s0 = e[0], s1 = e[1], s2 = e[2];
+        int a0 = 0, a1 = 1, a2 = 2;
+        if (s1 < s0) { const double t = s0; s0 = s1; s1 = t; const int q = a0; a0 = a1; a1 = q; }
+        if (s2 < s1) { const double t = s1; s1 = s2; s2 = t; const int q = a1; a1 = a2; a2 = q; }
+        if (s1 < s0) { const double t = s0; s0 = s1; s1 = t; const int q = a0; a0 = a1; a1 = q; }
+
+        double P = 0.0, tau = 1.0, pend = sig;
+        uint32_t passed = 0, refl = 0;
+        int mw_used = 0;
+        uint4 mw = make_uint4(0, 0, 0, 0);
+        bool go = true;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const double ek = k == 0 ? s0 : (k == 1 ? s1 : s2);
+            const int a = k == 0 ? a0 : (k == 1 ? a1 : a2);
+            go = go && (ek < pend);
+            if (go) {
+                ++nface;
+                const double va = a == 0 ? v[0] : (a == 1 ? v[1] : v[2]);
+                const int sgn = va > 0.0 ? 1 : -1;
+                const int cx = a == 0 ? wrap_step(ix, sgn, p.nx) : ix;
+                const int cy = a == 1 ? wrap_step(iy, sgn, p.ny) : iy;
+                const int cz = a == 2 ? wrap_step(iz, sgn, p.nz) : iz;
+                const int nl = lab[cx + p.nx * (cy + p.ny * cz)];
+                bool cross = true;
+                if (nl != l) {
+                    ++nhit;
+                    if (mw_used == 0) mw = philox4x32_10(i0, 1u, id.wlo, id.whi, id.k0, id.k1);
+                    const uint32_t word = mw_used == 0 ? mw.x : (mw_used == 1 ? mw.y : mw.z);
+                    ++mw_used;
+                    cross = word < p.thr[l * p.n_labels + nl];
+                    if (cross) {
+                        ++nperm;
+                        const double dtau = fmin((ek - P) / sig, tau);
+                        R = fma(p.dt * dtau, it2, R);
+                        tau -= dtau;
+                        P = ek;
+                        l = nl;
+                        sig = p.sigma[nl];
+                        it2 = p.inv_t2[nl];
+                        pend = fma(tau, sig, P);
+                    }
+                }
+                if (cross) {
+                    passed |= 1u << a;
+                    ix = cx;
+                    iy = cy;
+                    iz = cz;
+                } else {
+                    refl |= 1u << a;
+                }
+            }
+        }
+        const double lend = fma(tau, sig, P);
+        R = fma(p.dt * tau, it2, R);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const bool pos = v[a] > 0.0;
+            const double rest = (lend - e[a]) * v[a];  // signed travel after the face
+            double on;
+            if (refl & (1u << a)) on = (pos ? 1.0 : 0.0) - rest;
+            else if (passed & (1u << a)) on = (pos ? 0.0 : 1.0) + rest;
+            else on = fma(lend, v[a], o[a]);
+            on = fmin(fmax(on, 0.0), 1.0);
+            const double shift = (passed & (1u << a)) ? (pos ? 1.0 : -1.0) : 0.0;
+            d[a] += (on - o[a]) + shift;
+            o[a] = on;
+        }
+#pragma unroll
+        for (int q = 0; q < NS; ++q) {
+            const double g = p.gdt[static_cast<int64_t>(q) * p.n_steps + i0];
+            if (g != 0.0) {
+                ph[q][0] = fma(g, d[0], ph[q][0]);
+                ph[q][1] = fma(g, d[1], ph[q][1]);
+                ph[q][2] = fma(g, d[2], ph[q][2]);
+            }
+        }
+    }
+
+    // Per-walker record (layout of RMS_DUMP_WIDTH in rms.h).
+    __device__ __forceinline__ void finish(const WalkPlan& p, double* out) const {
+        out[0] = d[0] * p.voxel_um;
+        out[1] = d[1] * p.voxel_um;
+        out[2] = d[2] * p.voxel_um;
+        out[3] = R;
+        out[4] = l;
+        out[5] = ix;
+        out[6] = iy;
+        out[7] = iz;
+        out[8] = o[0];
+        out[9] = o[1];
+        out[10] = o[2];
+        out[11] = l0;
+        out[12] = nface;
+        out[13] = nhit;
+        out[14] = nperm;
+#pragma unroll
+        for (int q = 0; q < NS; ++q) {
+            out[15 + 3 * q] = ph[q][0] * p.voxel_um;
+            out[16 + 3 * q] = ph[q][1] * p.voxel_um;
+            out[17 + 3 * q] = ph[q][2] * p.voxel_um;
+        }
+    }
+};
+
+// ---------------------------------------------------------------------------
+// Mixed-precision form.
+// ---------------------------------------------------------------------------
+// (w + 1/2) 2^-32 rounded to the nearest float
+__device__ __forceinline__ float unit_open_f(uint32_t w) {
+    return static_cast<float>(unit_open(w));
+}
+
+template <typename LabelT, int NS>
+struct WalkerMixed {
+    static constexpr int kShapes = NS > 0 ? NS : 1;
+    int ix, iy, iz, l, l0;
+    uint32_t nface, nhit, nperm;
+    int n[3];     // voxels crossed per axis (signed), exact
+    float o[3];   // offset in the voxel, [0, 1]
+    float o0[3];  // offset at the start
+    float sig, it2;
+    float R, Rc;  // compensated R
+    float ph[kShapes][3], phc[kShapes][3];
+
+    __device__ __forceinline__ void init(const WalkPlan& p, const LabelT* __restrict__ lab,
+                                         const Ids& id) {
+        const Start s = draw_start(p, id);
+        ix = s.ix;
+        iy = s.iy;
+        iz = s.iz;
+        o[0] = o0[0] = unit_open_f(s.wox);
+        o[1] = o0[1] = unit_open_f(s.woy);
+        o[2] = o0[2] = unit_open_f(s.woz);
+        n[0] = n[1] = n[2] = 0;
+        l = l0 = lab[s.lin];
+        sig = p.sigma_f[l];
+        it2 = p.inv_t2_f[l];
+        R = Rc = 0.0f;
+#pragma unroll
+        for (int q = 0; q < kShapes; ++q)
+#pragma unroll
+            for (int a = 0; a < 3; ++a) ph[q][a] = phc[q][a] = 0.0f;
+        nface = nhit = nperm = 0;
+    }
+
+    __device__ __forceinline__ void step(const WalkPlan& p, const LabelT* __restrict__ lab,
+                                         uint32_t i0, uint32_t wa, uint32_t wb, const Ids& id) {
+        const double u1d = unit_open(wa);
+        const float u1 = static_cast<float>(u1d);
+        const float u2 = unit_open_f(wb);
+        const float cs = __builtin_amdgcn_cosf(u2);  // cos(2 pi u2)
+        const float sn = __builtin_amdgcn_sinf(u2);  // sin(2 pi u2)
+        const float rho = 2.0f * __builtin_sqrtf(u1 * (1.0f - u1));
+        const float v[3] = {rho * cs, rho * sn, static_cast<float>(1.0 - 2.0 * u1d)};
+
+        float e[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const float av = fabsf(v[a]);
+            const float gap = fmaxf(v[a] > 0.0f ? 1.0f - o[a] : o[a], 0.0f);
+            e[a] = av > 0.0f ? gap * __builtin_amdgcn_rcpf(av) : INFINITY;
+        }
+        float s0 = e[0], s1 = e[1], s2 = e[2];
+        int a0 = 0, a1 = 1, a2 = 2;
+        if (s1 < s0) { const float t = s0; s0 = s1; s1 = t; const int q = a0; a0 = a1; a1 = q; }
+        if (s2 < s1) { const float t = s1; s1 = s2; s2 = t; const int q = a1; a1 = a2; a2 = q; }
+        if (s1 < s0) { const float t = s0; s0 = s1; s1 = t; const int q = a0; a0 = a1; a1 = q; }
+
+        float P = 0.0f, tau = 1.0f, pend = sig;
+        uint32_t passed = 0, refl = 0;
+        int mw_used = 0;
+        uint4 mw = make_uint4(0, 0, 0, 0);
+        bool go = true;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const float ek = k == 0 ? s0 : (k == 1 ? s1 : s2);
+            const int a = k == 0 ? a0 : (k == 1 ? a1 : a2);
+            go = go && (ek < pend);
+            if (go) {
+                ++nface;
+                const float va = a == 0 ? v[0] : (a == 1 ? v[1] : v[2]);
+                const int sgn = va > 0.0f ? 1 : -1;
+                const int cx = a == 0 ? wrap_step(ix, sgn, p.nx) : ix;
+                const int cy = a == 1 ? wrap_step(iy, sgn, p.ny) : iy;
+                const int cz = a == 2 ? wrap_step(iz, sgn, p.nz) : iz;
+                const int nl = lab[cx + p.nx * (cy + p.ny * cz)];
+                bool cross = true;
+                if (nl != l) {
+                    ++nhit;
+                    if (mw_used == 0) mw = philox4x32_10(i0, 1u, id.wlo, id.whi, id.k0, id.k1);
+                    const uint32_t word = mw_used == 0 ? mw.x : (mw_used == 1 ? mw.y : mw.z);
+                    ++mw_used;
+                    cross = word < p.thr[l * p.n_labels + nl];
+                    if (cross) {
+                        ++nperm;
+                        const float dtau = fminf((ek - P) / sig, tau);
+                        nsum(R, Rc, static_cast<float>(p.dt) * dtau * it2);
+                        tau -= dtau;
+                        P = ek;
+                        l = nl;
+                        sig = p.sigma_f[nl];
+                        it2 = p.inv_t2_f[nl];
+                        pend = fmaf(tau, sig, P);
+                    }
+                }
+                if (cross) {
+                    passed |= 1u << a;
+                    ix = cx;
+                    iy = cy;
+                    iz = cz;
+                } else {
+                    refl |= 1u << a;
+                }
+            }
+        }
+        const float lend = fmaf(tau, sig, P);
+        nsum(R, Rc, static_cast<float>(p.dt) * tau * it2);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const bool pos = v[a] > 0.0f;
+            const float rest = (lend - e[a]) * v[a];
+            float on;
+            if (refl & (1u << a)) on = (pos ? 1.0f : 0.0f) - rest;
+            else if (passed & (1u << a)) on = (pos ? 0.0f : 1.0f) + rest;
+            else on = fmaf(lend, v[a], o[a]);
+            o[a] = fminf(fmaxf(on, 0.0f), 1.0f);
+            if (passed & (1u << a)) n[a] += pos ? 1 : -1;
+        }
+#pragma unroll
+        for (int q = 0; q < NS; ++q) {
+            const float g = p.gdt_f[static_cast<int64_t>(q) * p.n_steps + i0];
+            if (g != 0.0f) {
+#pragma unroll
+                for (int a = 0; a < 3; ++a)
+                    nsum(ph[q][a], phc[q][a], g * (static_cast<float>(n[a]) + (o[a] - o0[a])));
+            }
+        }
+    }
+
+    __device__ __forceinline__ void finish(const WalkPlan& p, double* out) const {
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+            out[a] = (static_cast<double>(n[a]) +
+                      (static_cast<double>(o[a]) - static_cast<double>(o0[a]))) * p.voxel_um;
+        out[3] = static_cast<double>(R) + static_cast<double>(Rc);
+        out[4] = l;
+        out[5] = ix;
+        out[6] = iy;
+        out[7] = iz;
+        out[8] = o[0];
+        out[9] = o[1];
+        out[10] = o[2];
+        out[11] = l0;
+        out[12] = nface;
+        out[13] = nhit;
+        out[14] = nperm;
+#pragma unroll
+        for (int q = 0; q < NS; ++q)
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+                out[15 + 3 * q + a] =
+                    (static_cast<double>(ph[q][a]) + static_cast<double>(phc[q][a])) * p.voxel_um;
+    }
+};
+
+// Steps [b, e) of one walker.  Direction words come two steps per Philox block.
+template <class Walker, typename LabelT>
+__device__ __forceinline__ void walk_range(const WalkPlan& p, const LabelT* __restrict__ lab,
+                                           Walker& W, uint32_t b, uint32_t e, const Ids& id) {
+    uint4 wd = make_uint4(0, 0, 0, 0);
+    for (uint32_t i0 = b; i0 < e; ++i0) {
+        const bool odd = (i0 & 1u) != 0;
+        if (!odd || i0 == b) wd = philox4x32_10(i0 >> 1, 0u, id.wlo, id.whi, id.k0, id.k1);
+        W.step(p, lab, i0, odd ? wd.z : wd.x, odd ? wd.w : wd.y, id);
+    }
+}
+
+}  // namespace dev
+}  // namespace rms

@@ -33,6 +33,16 @@ struct WalkPlan {
     const double* gdt;   // [n_shapes][n_steps] dt * G_s[i]
     const float* gdt_f;  // fp32 copy for the mixed form
     double* wstate;      // [n_walkers][kDumpFixed + 3 n_shapes] per-walker results
+    void* state;         // [n_walkers] resumable walker states (packed launches), or null
+};
+
+// One block of a packed launch: walkers [first_walker, first_walker + kBlock)
+// of plan `plan`, steps [step_begin, step_end).
+struct PackedItem {
+    int64_t first_walker;
+    int plan;
+    uint32_t step_begin, step_end;
+    uint32_t pad;
 };
 
 // Everything the reduction kernels read.
@@ -56,8 +66,16 @@ struct ReducePlan {
 
 constexpr int kAccFixed = 25;  // alpha, 6 M2, 15 M4, 3 counters
 
-hipError_t launch_walk_fp64(const WalkPlan& p, hipStream_t s);
-hipError_t launch_walk_mixed(const WalkPlan& p, hipStream_t s);
+// Whole walk of every walker of one run (precision RMS_FP64 or RMS_MIXED).
+hipError_t launch_walk(const WalkPlan& p, int precision, hipStream_t s);
+// A packed launch over several runs that share precision, label width and
+// shape count: each block advances its walkers by a range of steps, starting
+// from the stored state (or the start when step_begin == 0) and storing the
+// state again (or the final record when step_end == n_steps).
+hipError_t launch_walk_packed(const PackedItem* items, int n_items, const WalkPlan* plans,
+                              int precision, int label_bytes, int n_shapes, hipStream_t s);
+// Bytes of one resumable walker state.
+size_t walker_state_bytes(int precision, int label_bytes, int n_shapes);
 hipError_t launch_reduce(const ReducePlan& p, hipStream_t s);
 
 }  // namespace rms

@@ -130,7 +130,7 @@ def test_four_shapes_and_anisotropic_volume():
     lab = uniform_volume(5, 7, 3)
     lab[1, 2:5, 1:4] = 1
     n, dt = 400, 2e-4
-    wf = np.stack([pgse(n, dt, 0.01 * k, 0.03 * k) for k in (1, 2, 3, 4)])
+    wf = np.stack([pgse(n, dt, 0.005 * k, 0.015 * k) for k in (1, 2, 3, 4)])
     kap = np.array([[0, 0.3], [0.3, 0]])
     g, o = _both(lab, 0.1, np.array([1.0, 2.9]), kap, None, seed=2**40 + 5, n_walkers=513,
                  n_steps=n, dt=dt, waveform=wf, dirs=six_dirs(), bvals=[0.0, 0.2])
