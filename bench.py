@@ -62,7 +62,7 @@ def workload(name):
 
 def kernel_sha() -> str:
     h = hashlib.sha256()
-    for f in ("rms_walk.hip", "rms_walk_mixed.hip", "rms_internal.h"):
+    for f in ("rms_walk.hip", "rms_device.h", "rms_internal.h"):
         with open(os.path.join(ROOT, "paper_2012_06478_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -103,8 +103,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--precision", choices=("fp64", "mixed"), default="fp64")
     ap.add_argument("--workload", choices=WORKLOADS, default="ellipsoids200")
-    ap.add_argument("--cpu-sample-walkers", type=int, default=20_000)
+    ap.add_argument("--cpu-sample-walkers", type=int, default=250_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run only a plain 1 GiB device copy (3 times), to scale the "
+                         "FETCH_SIZE/WRITE_SIZE counters")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the walk needs no communication, and each "
@@ -117,6 +120,14 @@ def main():
     assert torch.cuda.is_available(), "bench needs a GPU"
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
+    if args.calibrate_copy:
+        a = torch.ones(2**30 // 4, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        log("[bench] copied 1 GiB three times")
+        return
     log(f"[bench] building workload {args.workload}")
     c = workload(args.workload)
     prec = rms.RMS_FP64 if args.precision == "fp64" else rms.RMS_MIXED

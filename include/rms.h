@@ -114,8 +114,11 @@ typedef struct {
     int64_t n_permeations;
     double max_perm_prob;       /* largest permeation probability in the run */
     double max_step_over_voxel; /* largest ds / voxel size in the run */
-    double wall_s;              /* host wall time of the call */
-    double kernel_ms;           /* walk kernel time, HIP events on the run's stream */
+    double wall_s;              /* rms_run: host wall time of the call; server: latency
+                                   from rms_server_submit to completion */
+    double kernel_ms;           /* rms_run: walk kernel time, HIP events on the run's
+                                   stream; server: 0 (launches are shared) */
+    double queue_s;             /* server: submit to admission; rms_run: 0 */
     double* walker_dump;
 } rms_result;
 
@@ -165,6 +168,75 @@ int rms_run(const rms_substrate* sub, const rms_params* params, uint64_t seed, i
             int64_t n_steps, double dt_ms, int n_shapes, const double* waveform, int n_dirs,
             const double* dirs, int n_b, const double* bvals, int precision, void* hip_stream,
             rms_result* out);
+
+/* ---------------------------------------------------------------------------
+ * Serving: continuous batching of simulation requests on one GPU.
+ *
+ * A server keeps the substrates its requests name resident (the caller keeps
+ * them alive until every request on them has completed), admits requests in
+ * arrival order while their device memory fits in the budget, and advances
+ * every admitted request by a slice of steps in one packed launch per slice
+ * (requests of different sizes share a launch, grouped by precision, label
+ * width and shape count).  A request that arrives while others run joins at
+ * the next slice boundary; a finished request's results are reduced at once
+ * and its memory freed for the next admission.  Walker trajectories depend only
+ * on (seed, walker, step) and each request is reduced on its own in a fixed
+ * order, so a request's results are bit-identical alone, in any mix and to
+ * rms_run with the same arguments.
+ * ------------------------------------------------------------------------- */
+typedef struct rms_server rms_server;
+typedef int64_t rms_ticket;
+
+/* One request: the arguments of rms_run.  Every array is copied at submit. */
+typedef struct {
+    const rms_substrate* substrate;
+    const rms_params* params; /* NULL = substrate defaults */
+    uint64_t seed;
+    int64_t n_walkers;
+    int64_t n_steps;
+    double dt_ms;
+    int n_shapes;
+    const double* waveform; /* [n_shapes][n_steps] */
+    int n_dirs;
+    const double* dirs;     /* [n_dirs][3] */
+    int n_b;
+    const double* bvals;    /* [n_b] */
+    int precision;          /* RMS_FP64 or RMS_MIXED */
+} rms_request;
+
+typedef struct {
+    int64_t submitted, completed, failed, pending, active;
+    int64_t launches;       /* packed walk launches so far */
+    int64_t walker_steps;   /* walker-steps of completed requests */
+    double busy_s;          /* device time of the packed launches (HIP events) */
+    size_t bytes_in_use, bytes_budget;
+} rms_server_stats;
+
+/* Create a server on the HIP device current at the call.
+ *   mem_budget_bytes  device memory the server may hold for admitted requests
+ *                     (0 = 3/4 of the device's free memory);
+ *   slice_steps       steps per slice (even, >= 2), or 0 to size each slice to
+ *                     about 4e9 walker-steps of the admitted requests. */
+int rms_server_create(size_t mem_budget_bytes, int slice_steps, rms_server** out);
+
+/* Queue a request; returns at once with its ticket.  Argument errors are
+ * reported here (as by rms_run); a request that cannot fit in the budget even
+ * alone returns RMS_E_BUSY. */
+int rms_server_submit(rms_server* srv, const rms_request* req, rms_ticket* ticket);
+
+/* *done = 1 once the request has completed or failed. */
+int rms_server_poll(rms_server* srv, rms_ticket ticket, int* done);
+
+/* Wait up to timeout_s seconds (< 0: forever) for a request, fill `out` as
+ * rms_run would (walker_dump is not available and must be NULL) and release
+ * the ticket.  RMS_E_TIMEOUT leaves the ticket valid; a failed request
+ * returns its error code and is released. */
+int rms_server_wait(rms_server* srv, rms_ticket ticket, double timeout_s, rms_result* out);
+
+int rms_server_stats_get(rms_server* srv, rms_server_stats* out);
+
+/* Stop the server: requests not yet complete fail, resources are freed. */
+void rms_server_destroy(rms_server* srv);
 
 #ifdef __cplusplus
 }

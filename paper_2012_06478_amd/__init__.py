@@ -53,8 +53,23 @@ class _Result(C.Structure):
                 ("b_disc", C.POINTER(C.c_double)), ("n_face_events", C.c_int64),
                 ("n_membrane_hits", C.c_int64), ("n_permeations", C.c_int64),
                 ("max_perm_prob", C.c_double), ("max_step_over_voxel", C.c_double),
-                ("wall_s", C.c_double), ("kernel_ms", C.c_double),
+                ("wall_s", C.c_double), ("kernel_ms", C.c_double), ("queue_s", C.c_double),
                 ("walker_dump", C.POINTER(C.c_double))]
+
+
+class _Request(C.Structure):
+    _fields_ = [("substrate", C.c_void_p), ("params", C.POINTER(_Params)), ("seed", C.c_uint64),
+                ("n_walkers", C.c_int64), ("n_steps", C.c_int64), ("dt_ms", C.c_double),
+                ("n_shapes", C.c_int), ("waveform", C.POINTER(C.c_double)), ("n_dirs", C.c_int),
+                ("dirs", C.POINTER(C.c_double)), ("n_b", C.c_int),
+                ("bvals", C.POINTER(C.c_double)), ("precision", C.c_int)]
+
+
+class _ServerStats(C.Structure):
+    _fields_ = [("submitted", C.c_int64), ("completed", C.c_int64), ("failed", C.c_int64),
+                ("pending", C.c_int64), ("active", C.c_int64), ("launches", C.c_int64),
+                ("walker_steps", C.c_int64), ("busy_s", C.c_double),
+                ("bytes_in_use", C.c_size_t), ("bytes_budget", C.c_size_t)]
 
 
 _lib = None
@@ -84,6 +99,18 @@ def _load():
                             C.c_double, C.c_int, dp, C.c_int, dp, C.c_int, dp, C.c_int,
                             C.c_void_p, C.POINTER(_Result)]
     lib.rms_run.restype = C.c_int
+    lib.rms_server_create.argtypes = [C.c_size_t, C.c_int, C.POINTER(C.c_void_p)]
+    lib.rms_server_create.restype = C.c_int
+    lib.rms_server_submit.argtypes = [C.c_void_p, C.POINTER(_Request), C.POINTER(C.c_int64)]
+    lib.rms_server_submit.restype = C.c_int
+    lib.rms_server_poll.argtypes = [C.c_void_p, C.c_int64, C.POINTER(C.c_int)]
+    lib.rms_server_poll.restype = C.c_int
+    lib.rms_server_wait.argtypes = [C.c_void_p, C.c_int64, C.c_double, C.POINTER(_Result)]
+    lib.rms_server_wait.restype = C.c_int
+    lib.rms_server_stats_get.argtypes = [C.c_void_p, C.POINTER(_ServerStats)]
+    lib.rms_server_stats_get.restype = C.c_int
+    lib.rms_server_destroy.argtypes = [C.c_void_p]
+    lib.rms_server_destroy.restype = None
     _lib = lib
     return lib
 
@@ -92,7 +119,8 @@ def exported_symbols() -> list[str]:
     """Names the library exports through the C ABI (for load checks)."""
     lib = _load()
     names = ["rms_abi_version", "rms_last_error", "rms_create_substrate",
-             "rms_destroy_substrate", "rms_run"]
+             "rms_destroy_substrate", "rms_run", "rms_server_create", "rms_server_submit",
+             "rms_server_poll", "rms_server_wait", "rms_server_stats_get", "rms_server_destroy"]
     return [n for n in names if hasattr(lib, n)]
 
 
@@ -169,6 +197,55 @@ def _stream_handle(stream):
     return int(stream.cuda_stream)  # torch.cuda.Stream (HIP stream on ROCm)
 
 
+def _protocol(n_steps, waveform, dirs, bvals):
+    W = (np.zeros((0, n_steps)) if waveform is None
+         else np.ascontiguousarray(np.atleast_2d(waveform), np.float64))
+    g = (np.zeros((0, 3)) if dirs is None
+         else np.ascontiguousarray(dirs, np.float64).reshape(-1, 3))
+    b = np.zeros(0) if bvals is None else np.ascontiguousarray(bvals, np.float64)
+    return W, g, b
+
+
+def _params(params, keep):
+    if params is None:
+        return None
+    Dv = np.ascontiguousarray(params["D"], np.float64)
+    kap = params.get("kappa")
+    kap = None if kap is None else np.ascontiguousarray(kap, np.float64).reshape(-1)
+    t2 = params.get("T2")
+    t2 = None if t2 is None else np.ascontiguousarray(t2, np.float64)
+    keep += [Dv, kap, t2]
+    return _Params(Dv.size, _dptr(Dv), _dptr(kap), _dptr(t2))
+
+
+class _ResultBuffers:
+    def __init__(self, ns, nb, nd):
+        self.shape = (ns, nb, nd)
+        self.sig = np.zeros(max(ns * nb * nd, 1) * 2)
+        self.Dd = np.zeros(max(nd, 1))
+        self.Kd = np.zeros(max(nd, 1))
+        self.bd = np.zeros(max(ns, 1))
+        self.res = _Result()
+        self.res.signal = _dptr(self.sig)
+        self.res.D_dir = _dptr(self.Dd)
+        self.res.K_dir = _dptr(self.Kd)
+        self.res.b_disc = _dptr(self.bd)
+        self.res.walker_dump = None
+
+    def to_dict(self):
+        ns, nb, nd = self.shape
+        res, sig = self.res, self.sig
+        return dict(
+            signal=(sig[0::2] + 1j * sig[1::2])[: ns * nb * nd].reshape(ns, nb, nd),
+            m2=np.array(res.m2[:]), m4=np.array(res.m4[:]), D=self.Dd[:nd].copy(),
+            K=self.Kd[:nd].copy(), sum_alpha=res.sum_alpha, b_disc=self.bd[:ns].copy(),
+            n_face_events=res.n_face_events, n_membrane_hits=res.n_membrane_hits,
+            n_permeations=res.n_permeations, max_perm_prob=res.max_perm_prob,
+            max_step_over_voxel=res.max_step_over_voxel, wall_s=res.wall_s,
+            kernel_ms=res.kernel_ms, queue_s=res.queue_s,
+        )
+
+
 def rms_run(sub: Substrate, *, seed, n_walkers, n_steps, dt, waveform=None, dirs=None,
             bvals=None, precision=RMS_FP64, params=None, stream=None, dump=False) -> dict:
     """Run the walk; returns a dict of numpy results (see ``include/rms.h``).
@@ -177,52 +254,70 @@ def rms_run(sub: Substrate, *, seed, n_walkers, n_steps, dt, waveform=None, dirs
     substrate's tissue parameters.  ``stream``: a torch.cuda.Stream or a raw
     hipStream_t (int); None runs on the null stream."""
     lib = _load()
-    W = (np.zeros((0, n_steps)) if waveform is None
-         else np.ascontiguousarray(np.atleast_2d(waveform), np.float64))
-    ns = W.shape[0]
-    g = (np.zeros((0, 3)) if dirs is None
-         else np.ascontiguousarray(dirs, np.float64).reshape(-1, 3))
-    b = np.zeros(0) if bvals is None else np.ascontiguousarray(bvals, np.float64)
-    nd, nb = g.shape[0], b.size
+    W, g, b = _protocol(n_steps, waveform, dirs, bvals)
     keep = []
-    pp = None
-    if params is not None:
-        Dv = np.ascontiguousarray(params["D"], np.float64)
-        kap = params.get("kappa")
-        kap = None if kap is None else np.ascontiguousarray(kap, np.float64).reshape(-1)
-        t2 = params.get("T2")
-        t2 = None if t2 is None else np.ascontiguousarray(t2, np.float64)
-        keep += [Dv, kap, t2]
-        pp = _Params(Dv.size, _dptr(Dv), _dptr(kap), _dptr(t2))
-    sig = np.zeros(max(ns * nb * nd, 1) * 2)
-    Dd = np.zeros(max(nd, 1))
-    Kd = np.zeros(max(nd, 1))
-    bd = np.zeros(max(ns, 1))
-    wd = np.zeros((int(n_walkers), RMS_DUMP_FIXED + 3 * ns)) if dump else None
-    res = _Result()
-    res.signal = _dptr(sig)
-    res.D_dir = _dptr(Dd)
-    res.K_dir = _dptr(Kd)
-    res.b_disc = _dptr(bd)
-    res.walker_dump = _dptr(wd) if wd is not None else None
+    pp = _params(params, keep)
+    rb = _ResultBuffers(W.shape[0], b.size, g.shape[0])
+    wd = np.zeros((int(n_walkers), RMS_DUMP_FIXED + 3 * W.shape[0])) if dump else None
+    rb.res.walker_dump = _dptr(wd) if wd is not None else None
     rc = lib.rms_run(sub.handle, None if pp is None else C.byref(pp), int(seed) & (2**64 - 1),
-                     int(n_walkers), int(n_steps), float(dt), ns, _dptr(W), nd, _dptr(g), nb,
-                     _dptr(b), int(precision), _stream_handle(stream), C.byref(res))
+                     int(n_walkers), int(n_steps), float(dt), W.shape[0], _dptr(W), g.shape[0],
+                     _dptr(g), b.size, _dptr(b), int(precision), _stream_handle(stream),
+                     C.byref(rb.res))
     _check(rc)
-    out = dict(
-        signal=(sig[0::2] + 1j * sig[1::2])[: ns * nb * nd].reshape(ns, nb, nd),
-        m2=np.array(res.m2[:]), m4=np.array(res.m4[:]), D=Dd[:nd].copy(), K=Kd[:nd].copy(),
-        sum_alpha=res.sum_alpha, b_disc=bd[:ns].copy(), n_face_events=res.n_face_events,
-        n_membrane_hits=res.n_membrane_hits, n_permeations=res.n_permeations,
-        max_perm_prob=res.max_perm_prob, max_step_over_voxel=res.max_step_over_voxel,
-        wall_s=res.wall_s, kernel_ms=res.kernel_ms,
-    )
+    out = rb.to_dict()
     if wd is not None:
         out["dump"] = wd
-        out["phase"] = wd[:, RMS_DUMP_FIXED:].reshape(int(n_walkers), ns, 3)
+        out["phase"] = wd[:, RMS_DUMP_FIXED:].reshape(int(n_walkers), W.shape[0], 3)
     return out
 
 
+# ------------------------------------------------------------------ server --
+
+def rms_server_create(mem_budget_bytes: int = 0, slice_steps: int = 0):
+    h = C.c_void_p()
+    _check(_load().rms_server_create(int(mem_budget_bytes), int(slice_steps), C.byref(h)))
+    return h
+
+
+def rms_server_submit(srv, sub: Substrate, *, seed, n_walkers, n_steps, dt, waveform=None,
+                      dirs=None, bvals=None, precision=RMS_FP64, params=None):
+    """Queue a request; returns (ticket, shape of its signal array)."""
+    lib = _load()
+    W, g, b = _protocol(n_steps, waveform, dirs, bvals)
+    keep = []
+    pp = _params(params, keep)
+    q = _Request(sub.handle, None if pp is None else C.pointer(pp), int(seed) & (2**64 - 1),
+                 int(n_walkers), int(n_steps), float(dt), W.shape[0], _dptr(W), g.shape[0],
+                 _dptr(g), b.size, _dptr(b), int(precision))
+    t = C.c_int64()
+    _check(lib.rms_server_submit(srv, C.byref(q), C.byref(t)))
+    return t.value, (W.shape[0], b.size, g.shape[0])
+
+
+def rms_server_poll(srv, ticket: int) -> bool:
+    d = C.c_int()
+    _check(_load().rms_server_poll(srv, int(ticket), C.byref(d)))
+    return bool(d.value)
+
+
+def rms_server_wait(srv, ticket: int, shape, timeout_s: float = -1.0) -> dict:
+    rb = _ResultBuffers(*shape)
+    _check(_load().rms_server_wait(srv, int(ticket), float(timeout_s), C.byref(rb.res)))
+    return rb.to_dict()
+
+
+def rms_server_stats_get(srv) -> dict:
+    st = _ServerStats()
+    _check(_load().rms_server_stats_get(srv, C.byref(st)))
+    return {k: getattr(st, k) for k, _ in _ServerStats._fields_}
+
+
+def rms_server_destroy(srv) -> None:
+    _load().rms_server_destroy(srv)
+
+
 __all__ = ["rms_abi_version", "rms_last_error", "rms_create_substrate", "rms_destroy_substrate",
-           "rms_run", "Substrate", "RmsError", "RMS_FP64", "RMS_MIXED", "exported_symbols",
+           "rms_run", "rms_server_create", "rms_server_submit", "rms_server_poll",
+           "rms_server_wait", "rms_server_stats_get", "rms_server_destroy", "Substrate", "RmsError", "RMS_FP64", "RMS_MIXED", "exported_symbols",
            "DUMP_FIELDS"]

@@ -1,0 +1,83 @@
+// Host-side internals shared by rms_run (rms_api.cpp) and the server
+// (rms_server.cpp): the substrate object, per-run preparation and the device
+// buffers of one run.  Not installed.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "rms.h"
+#include "rms_internal.h"
+
+struct rms_substrate {
+    int device = 0;
+    int label_bytes = 1;
+    int64_t dims[3] = {0, 0, 0};
+    double voxel_um = 0.0;
+    int n_labels = 0;
+    std::vector<double> D, kappa, T2;
+    std::vector<uint8_t> dead;
+    void* d_labels = nullptr;
+    uint32_t* d_allowed = nullptr;
+    uint32_t n_allowed = 0;
+};
+
+namespace rms {
+
+// Records a failure for rms_last_error() on the calling thread; returns code.
+int fail(int code, const std::string& msg);
+int hip_fail(const char* what, hipError_t e);
+void clear_error();
+const char* last_error();
+
+// Everything a run needs that the host computes: validated sizes, per-label
+// tables (section 2.1.3, 2.1.4) and per-shape waveform scaling (section 2.3).
+struct RunSetup {
+    const rms_substrate* sub = nullptr;
+    uint64_t seed = 0;
+    int64_t n_walkers = 0, n_steps = 0;
+    double dt = 0.0;
+    int precision = RMS_FP64;
+    int n_shapes = 0, n_dirs = 0, n_b = 0, n_sig = 0;
+    int n_acc = 0, width = 0, n_blocks = 0, n_res = 0;
+    std::vector<double> sigma, inv_t2;
+    std::vector<float> sigma_f, inv_t2_f;
+    std::vector<uint32_t> thr;
+    double max_sigma = 0.0, max_p = 0.0;
+    std::vector<double> gdt;
+    std::vector<float> gdt_f;
+    std::vector<double> b_disc, kg, unit;
+    std::vector<int> sig_shape;
+};
+
+// Validates the arguments of rms_run and fills `out`.  Returns RMS_OK or an
+// RMS_E_* code (with the message recorded).
+int prepare_run(const rms_substrate* sub, const rms_params* params, uint64_t seed,
+                int64_t n_walkers, int64_t n_steps, double dt_ms, int n_shapes,
+                const double* waveform, int n_dirs, const double* dirs, int n_b,
+                const double* bvals, int precision, RunSetup& out);
+
+// Device bytes a run holds while it is in flight (resumable: with the walker
+// states a packed launch keeps between slices).
+size_t device_bytes(const RunSetup& r, bool resumable);
+
+// The device buffers of one run, uploaded on stream s and released
+// stream-ordered on s.
+struct DeviceRun {
+    hipStream_t s = nullptr;
+    std::vector<void*> ptrs;
+    WalkPlan wp{};
+    ReducePlan rp{};
+    int create(const rms_substrate& sub, const RunSetup& r, bool resumable, hipStream_t s);
+    void release();
+    ~DeviceRun() { release(); }
+};
+
+// Copies the reduced results (device layout of ReducePlan::result) into the
+// caller's rms_result.
+void fill_result(const RunSetup& r, const double* res, rms_result* out);
+
+}  // namespace rms
