@@ -96,6 +96,150 @@ def cpu_baseline(c, sample_walkers: int):
                       f"{el:.1f} s on {threads} threads"}
 
 
+def served_substrates():
+    """Sixteen resident substrates, n^3 uint16 with n = 64 ... 400 (geometric),
+    alternating ellipsoid packings (cells scaled with volume) and axon bundles
+    (tubes scaled with cross-section)."""
+    from rms_inputs import ellipsoid_packing, axon_bundle
+    out = []
+    for k, n in enumerate(np.round(np.geomspace(64, 400, 16)).astype(int)):
+        n = int(n)
+        if k % 2 == 0:
+            lab, _ = ellipsoid_packing(n=n, n_cells=max(1, round(120 * (n / 200) ** 3)),
+                                       seed=100 + k)
+        else:
+            lab, _ = axon_bundle(n, n, n, n_axons=max(1, round(300 * (n / 400) ** 2)),
+                                 seed=100 + k)
+        out.append(lab)
+    return out
+
+
+def served_requests(n_sub, count=256, seed=5):
+    """The request trace: walkers log-uniform in [1e4, 2e6], steps uniform in
+    [1e3, 2e4], kappa uniform in [0, 0.05], D 2 intra / 2.5 extra, T2 80/60,
+    dt 2e-4, PGSE (delta T/4, Delta 3T/4), 6-30 directions x 2-6 b values."""
+    from rms_inputs import fibonacci_hemisphere, pgse
+    rng = np.random.default_rng(seed)
+    reqs = []
+    for r in range(count):
+        n_steps = int(rng.integers(1000, 20001))
+        n_steps -= n_steps % 4
+        dt = 2e-4
+        T = n_steps * dt
+        nb = int(rng.integers(2, 7))
+        reqs.append(dict(sub=int(rng.integers(0, n_sub)), seed=1000 + r,
+                         n_walkers=int(np.exp(rng.uniform(np.log(1e4), np.log(2e6)))),
+                         n_steps=n_steps, dt=dt, kappa=float(rng.uniform(0.0, 0.05)),
+                         waveform=pgse(n_steps, dt, T / 4, 3 * T / 4),
+                         dirs=fibonacci_hemisphere(int(rng.integers(6, 31))),
+                         bvals=np.linspace(0.0, 2.0, nb)))
+    return reqs
+
+
+def _tissue(n_labels, kappa):
+    D = np.full(n_labels, 2.0)
+    D[0] = 2.5
+    T2 = np.full(n_labels, 80.0)
+    T2[0] = 60.0
+    k = np.zeros((n_labels, n_labels))
+    k[0, 1:] = kappa
+    k[1:, 0] = kappa
+    return dict(D=D, kappa=k, T2=T2)
+
+
+def serve(args):
+    """Continuous-batching benchmark: Poisson arrivals at 0.7 of the measured
+    capacity; latency = completion - arrival."""
+    import torch
+    import paper_2012_06478_amd as rms
+    assert torch.cuda.is_available(), "bench needs a GPU"
+    torch.cuda.set_device(0)
+    t0 = time.perf_counter()
+    labs = served_substrates()
+    log(f"[serve] 16 substrates generated in {time.perf_counter() - t0:.1f} s "
+        f"({sum(l.nbytes for l in labs) / 1e6:.0f} MB)")
+    subs = []
+    for lab in labs:
+        L = int(lab.max()) + 1
+        t = _tissue(L, 0.0)
+        subs.append(rms.rms_create_substrate(lab, 0.1, t["D"], t["kappa"], t["T2"]))
+    nl = [int(lab.max()) + 1 for lab in labs]
+    reqs = served_requests(len(subs), args.serve_requests)
+    prec = rms.RMS_MIXED if args.precision == "mixed" else rms.RMS_FP64
+
+    def submit(srv, q):
+        return rms.rms_server_submit(srv, subs[q["sub"]], seed=q["seed"],
+                                     n_walkers=q["n_walkers"], n_steps=q["n_steps"], dt=q["dt"],
+                                     waveform=q["waveform"], dirs=q["dirs"], bvals=q["bvals"],
+                                     precision=prec, params=_tissue(nl[q["sub"]], q["kappa"]))
+
+    srv = rms.rms_server_create(0, 0)
+    try:
+        # capacity: a closed batch of the first 16 requests
+        t0 = time.perf_counter()
+        tk = [submit(srv, q) for q in reqs[:16]]
+        for t, sh in tk:
+            rms.rms_server_wait(srv, t, sh)
+        cap_el = time.perf_counter() - t0
+        cap = sum(q["n_walkers"] * q["n_steps"] for q in reqs[:16]) / cap_el
+        log(f"[serve] capacity {cap:.3e} walker-steps/s (16 requests in {cap_el:.2f} s)")
+        work = np.array([q["n_walkers"] * q["n_steps"] for q in reqs], float)
+        rate = args.serve_load * cap / work.mean()  # requests per second
+        rng = np.random.default_rng(11)
+        arrivals = np.cumsum(rng.exponential(1.0 / rate, size=len(reqs)))
+        log(f"[serve] {len(reqs)} requests, {work.sum():.3e} walker-steps, Poisson rate "
+            f"{rate:.2f}/s over ~{arrivals[-1]:.1f} s")
+        st0 = rms.rms_server_stats_get(srv)
+        tickets = []
+        start = time.perf_counter()
+        for i, q in enumerate(reqs):
+            delay = start + arrivals[i] - time.perf_counter()
+            if delay > 0:
+                time.sleep(delay)
+            tickets.append(submit(srv, q))
+            if i % 32 == 31:
+                log(f"[serve] submitted {i + 1}")
+        results = []
+        for i, (t, sh) in enumerate(tickets):
+            results.append(rms.rms_server_wait(srv, t, sh))
+        end = time.perf_counter()
+        st = rms.rms_server_stats_get(srv)
+    finally:
+        rms.rms_server_destroy(srv)
+    lat = np.array([r["wall_s"] for r in results])
+    queue = np.array([r["queue_s"] for r in results])
+    agg = work.sum() / (end - start)
+    # accuracy of the served results against the plain fp64 walk
+    err = 0.0
+    for i in range(0, len(reqs), max(1, len(reqs) // args.serve_check)):
+        q = reqs[i]
+        if q["n_walkers"] * q["n_steps"] > 4e9:
+            continue
+        ref = rms.rms_run(subs[q["sub"]], seed=q["seed"], n_walkers=q["n_walkers"],
+                          n_steps=q["n_steps"], dt=q["dt"], waveform=q["waveform"],
+                          dirs=q["dirs"], bvals=q["bvals"], precision=rms.RMS_FP64,
+                          params=_tissue(nl[q["sub"]], q["kappa"]))
+        err = max(err, float(np.max(np.abs(ref["signal"] - results[i]["signal"]))))
+    for s_ in subs:
+        s_.close()
+    line = {
+        "metric": "served walker-steps/s", "value": agg, "unit": "walker-steps/s",
+        "n_gpus": 1, "higher_is_better": True, "data": "synthetic",
+        "dtype": "f32+i32 walk, f64 reductions" if prec == rms.RMS_MIXED else "f64",
+        "p50_latency_s": float(np.percentile(lat, 50)),
+        "p99_latency_s": float(np.percentile(lat, 99)),
+        "p50_queue_s": float(np.percentile(queue, 50)),
+        "p99_queue_s": float(np.percentile(queue, 99)),
+        "capacity_walker_steps_per_s": cap, "offered_load": args.serve_load,
+        "device_busy_frac": (st["busy_s"] - st0["busy_s"]) / (end - start),
+        "launches": st["launches"] - st0["launches"],
+        "max_signal_err_vs_fp64": err,
+        "config": {"workload": "16 resident substrates 64^3..400^3 u16, "
+                               f"{len(reqs)} Poisson requests", "precision": args.precision},
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -105,6 +249,12 @@ def main():
     ap.add_argument("--workload", choices=WORKLOADS, default="ellipsoids200")
     ap.add_argument("--cpu-sample-walkers", type=int, default=250_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serve", action="store_true",
+                    help="continuous-batching benchmark over a Poisson request trace")
+    ap.add_argument("--serve-requests", type=int, default=256)
+    ap.add_argument("--serve-load", type=float, default=0.7)
+    ap.add_argument("--serve-check", type=int, default=8,
+                    help="requests re-run in fp64 to report the served signal error")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run only a plain 1 GiB device copy (3 times), to scale the "
                          "FETCH_SIZE/WRITE_SIZE counters")
@@ -113,6 +263,12 @@ def main():
         print("bench.py runs on one GPU only: the walk needs no communication, and each "
               "GPU would run the same kernel on its own share of walkers.", file=sys.stderr)
         sys.exit(2)
+
+    if args.serve:
+        if args.precision == "fp64" and "--precision" not in sys.argv:
+            args.precision = "mixed"  # the served form runs the mixed-precision walk
+        serve(args)
+        return
 
     import torch
     import paper_2012_06478_amd as rms

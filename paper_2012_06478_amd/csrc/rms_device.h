@@ -75,6 +75,70 @@ __device__ __forceinline__ int wrap_step(int c, int d, int n) {
     return c >= n ? c - n : c;
 }
 
+// cos(2 pi u) and sin(2 pi u) for u in [0, 1] to about 1 ulp.  Reduction to a
+// quarter turn is exact: x = 4u, k = rint(x), r = x - k in [-1/2, 1/2], so
+// 2 pi u = k pi/2 + a with a = r pi/2, |a| <= pi/4.  sin a and cos a are the
+// Taylor series of sine and cosine through a^17 and a^18 (the next terms are
+// below 1e-19 on |a| <= pi/4), evaluated by Horner's rule in a^2; the quadrant
+// k mod 4 then permutes and negates them.
+__host__ __device__ __forceinline__ void sincos_2pi(double u, double* s_out, double* c_out) {
+    const double x = 4.0 * u;
+    const double k = rint(x);
+    const double a = (x - k) * 1.5707963267948966;  // pi/2
+    const double z = a * a;
+    // sin a = a sum_k (-1)^k z^k / (2k+1)!,  k = 0..8
+    double ps = 1.0 / 355687428096000.0;              // 1/17!
+    ps = fma(z, ps, -1.0 / 1307674368000.0);          // 1/15!
+    ps = fma(z, ps, 1.0 / 6227020800.0);              // 1/13!
+    ps = fma(z, ps, -1.0 / 39916800.0);               // 1/11!
+    ps = fma(z, ps, 1.0 / 362880.0);                  // 1/9!
+    ps = fma(z, ps, -1.0 / 5040.0);                   // 1/7!
+    ps = fma(z, ps, 1.0 / 120.0);                     // 1/5!
+    ps = fma(z, ps, -1.0 / 6.0);                      // 1/3!
+    const double sa = fma(a * z, ps, a);
+    // cos a = sum_k (-1)^k z^k / (2k)!,  k = 0..9
+    double pc = -1.0 / 6402373705728000.0;            // 1/18!
+    pc = fma(z, pc, 1.0 / 20922789888000.0);          // 1/16!
+    pc = fma(z, pc, -1.0 / 87178291200.0);            // 1/14!
+    pc = fma(z, pc, 1.0 / 479001600.0);               // 1/12!
+    pc = fma(z, pc, -1.0 / 3628800.0);                // 1/10!
+    pc = fma(z, pc, 1.0 / 40320.0);                   // 1/8!
+    pc = fma(z, pc, -1.0 / 720.0);                    // 1/6!
+    pc = fma(z, pc, 1.0 / 24.0);                      // 1/4!
+    pc = fma(z, pc, -0.5);                            // 1/2!
+    const double ca = fma(z, pc, 1.0);
+    const int q = static_cast<int>(k) & 3;
+    const double cs = (q & 1) ? sa : ca;
+    const double sn = (q & 1) ? ca : sa;
+    *c_out = (q == 1 || q == 2) ? -cs : cs;
+    *s_out = (q >= 2) ? -sn : sn;
+}
+
+// 1/x for finite normal x > 0: the hardware reciprocal estimate refined by two
+// Newton steps r <- r + r (1 - x r) (within an ulp or two of the correctly
+// rounded quotient).
+__device__ __forceinline__ double recip_pos(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
+
+// sqrt(y) for finite normal y > 0: the hardware reciprocal square root
+// estimate, one coupled Newton step on (sqrt y, 1/(2 sqrt y)) and a final
+// residual correction (Goldschmidt's iteration).
+__device__ __forceinline__ double sqrt_pos(double y) {
+    const double r = __builtin_amdgcn_rsq(y);
+    double g = y * r;
+    double h = 0.5 * r;
+    const double e = fma(-g, h, 0.5);
+    g = fma(g, e, g);
+    h = fma(h, e, h);
+    const double d = fma(-g, g, y);
+    return fma(d, h, g);
+}
+
 // Neumaier compensated accumulation: s + c carries the sum of every x added.
 __device__ __forceinline__ void nsum(float& s, float& c, float x) {
     const float t = s + x;
@@ -153,8 +217,8 @@ struct WalkerF64 {
         const double u1 = unit_open(wa);
         const double u2 = unit_open(wb);
         double sn, cs;
-        sincospi(2.0 * u2, &sn, &cs);
-        const double rho = 2.0 * sqrt(u1 * (1.0 - u1));
+        sincos_2pi(u2, &sn, &cs);
+        const double rho = 2.0 * sqrt_pos(u1 * (1.0 - u1));
         const double v[3] = {rho * cs, rho * sn, 1.0 - 2.0 * u1};
 
         // path length to the face each axis moves toward
@@ -163,7 +227,7 @@ struct WalkerF64 {
         for (int a = 0; a < 3; ++a) {
             const double av = fabs(v[a]);
             const double gap = fmax(v[a] > 0.0 ? 1.0 - o[a] : o[a], 0.0);
-            e[a] = av > 0.0 ? gap / av : INFINITY;
+            e[a] = av > 0.0 ? gap * recip_pos(av) : INFINITY;
         }
         // stable sort of (e, axis): ties keep x < y < z
         double s0 = e[0], s1 = e[1], s2 = e[2];

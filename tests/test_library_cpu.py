@@ -53,3 +53,46 @@ def test_header_limits_match_binding():
     for name in ("RMS_MAX_SHAPES", "RMS_MAX_SIGNALS", "RMS_MAX_LABELS", "RMS_DUMP_FIXED"):
         v = int(re.search(rf"#define {name} (\d+)", text).group(1))
         assert getattr(rms, name) == v
+
+
+_SINCOS_PROBE = r"""
+#include "rms_device.h"
+#include <cmath>
+#include <cstdio>
+#include <random>
+int main() {
+    std::mt19937_64 g(1);
+    double maxe = 0.0;
+    for (int i = 0; i < 2000000; ++i) {
+        const uint32_t w = i < 4 ? (uint32_t[]){0u, 0x3fffffffu, 0x80000000u, 0xffffffffu}[i]
+                                 : static_cast<uint32_t>(g());
+        const double u = (static_cast<double>(w) + 0.5) * 0x1p-32;
+        double s, c;
+        rms::dev::sincos_2pi(u, &s, &c);
+        const long double th = 2.0L * 3.14159265358979323846264338327950288L * u;
+        maxe = std::fmax(maxe, std::fabs(static_cast<double>(sinl(th) - s)));
+        maxe = std::fmax(maxe, std::fabs(static_cast<double>(cosl(th) - c)));
+    }
+    std::printf("%.3e\n", maxe);
+    return 0;
+}
+"""
+
+
+def test_device_sincos_2pi_accuracy(tmp_path):
+    """The walker's cos/sin of 2 pi u (quarter-turn reduction + Taylor series)
+    against long-double libm on the host build of the same function."""
+    import shutil
+    import subprocess
+    if shutil.which("hipcc") is None:
+        pytest.skip("hipcc not available")
+    src = tmp_path / "sc.cpp"
+    exe = tmp_path / "sc"
+    src.write_text(_SINCOS_PROBE)
+    csrc = os.path.join(ROOT, "paper_2012_06478_amd", "csrc")
+    subprocess.check_call(["hipcc", "-O2", "-std=c++17", "-I", os.path.join(ROOT, "include"),
+                           "-I", csrc, "-o", str(exe), str(src)],
+                          stdout=subprocess.DEVNULL, stderr=subprocess.DEVNULL, timeout=300)
+    err = float(subprocess.run([str(exe)], capture_output=True, text=True, check=True,
+                               timeout=120).stdout)
+    assert err < 4e-16
