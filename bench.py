@@ -240,6 +240,48 @@ def serve(args):
     print(json.dumps(line), flush=True)
 
 
+def precision_report(args):
+    """The mixed-precision form against the fp64 form on the same inputs (the
+    fp64 form matches the oracle walker by walker): error per b value, per
+    direction and per moment, and both throughputs."""
+    import torch
+    import paper_2012_06478_amd as rms
+    assert torch.cuda.is_available(), "bench needs a GPU"
+    torch.cuda.set_device(0)
+    log(f"[precision] building workload {args.workload}")
+    c = workload(args.workload)
+    sub = rms.rms_create_substrate(c["labels"], c["voxel_um"], c["D"], c["kappa"], c["T2"],
+                                   c.get("dead"))
+    run = dict(seed=c["seed"], n_walkers=c["n_walkers"], n_steps=c["n_steps"], dt=c["dt"],
+               waveform=c["waveform"], dirs=c["dirs"], bvals=c["bvals"])
+    out = {}
+    for name, prec in (("fp64", rms.RMS_FP64), ("mixed", rms.RMS_MIXED)):
+        r = rms.rms_run(sub, precision=prec, **run)
+        out[name] = r
+        log(f"[precision] {name}: {r['wall_s']:.2f} s, walk kernel {r['kernel_ms']:.0f} ms")
+    sub.close()
+    a, b = out["fp64"], out["mixed"]
+    dS = np.abs(a["signal"] - b["signal"])  # [shape][b][dir]
+    ws = c["n_walkers"] * c["n_steps"]
+    line = {
+        "metric": "mixed-precision error vs fp64", "workload": c["name"],
+        "n_walkers": c["n_walkers"], "n_steps": c["n_steps"],
+        "max_abs_signal_err": float(dS.max()),
+        "max_abs_signal_err_per_b": [float(x) for x in dS.max(axis=(0, 2))],
+        "max_abs_signal_err_per_dir": [float(x) for x in dS.max(axis=(0, 1))],
+        "bvals": [float(x) for x in c["bvals"]],
+        "m2_rel_err": [float(x) for x in np.abs(a["m2"] - b["m2"]) / np.max(np.abs(a["m2"]))],
+        "m4_rel_err": [float(x) for x in np.abs(a["m4"] - b["m4"]) / np.max(np.abs(a["m4"]))],
+        "D_rel_err_max": float(np.max(np.abs(a["D"] - b["D"]) / np.abs(a["D"]))),
+        "K_abs_err_max": float(np.max(np.abs(a["K"] - b["K"]))),
+        "sum_alpha_rel_err": abs(a["sum_alpha"] - b["sum_alpha"]) / a["sum_alpha"],
+        "fp64_walker_steps_per_s": ws / a["wall_s"],
+        "mixed_walker_steps_per_s": ws / b["wall_s"],
+        "fp64_kernel_ms": a["kernel_ms"], "mixed_kernel_ms": b["kernel_ms"],
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -249,6 +291,8 @@ def main():
     ap.add_argument("--workload", choices=WORKLOADS, default="ellipsoids200")
     ap.add_argument("--cpu-sample-walkers", type=int, default=250_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--precision-report", action="store_true",
+                    help="mixed vs fp64 on the same inputs: error per b, direction, moment")
     ap.add_argument("--serve", action="store_true",
                     help="continuous-batching benchmark over a Poisson request trace")
     ap.add_argument("--serve-requests", type=int, default=256)
@@ -264,6 +308,9 @@ def main():
               "GPU would run the same kernel on its own share of walkers.", file=sys.stderr)
         sys.exit(2)
 
+    if args.precision_report:
+        precision_report(args)
+        return
     if args.serve:
         if args.precision == "fp64" and "--precision" not in sys.argv:
             args.precision = "mixed"  # the served form runs the mixed-precision walk

@@ -17,8 +17,11 @@
  *     64-bit seed, with counter words (index, substream, walker_lo, walker_hi):
  *       substream 0: step directions; block j feeds steps 2j+1 (words 0,1) and
  *                    2j+2 (words 2,3);
- *       substream 1: membrane decisions of step i, block index i-1, words used
- *                    in order of the step's membrane encounters;
+ *       substream 1: the first membrane decision of step i uses word (i-1) mod 4
+ *                    of block (i-1)/4;
+ *       substream 3: the second and third membrane decisions of step i (rare:
+ *                    two or three membranes met in one step) use words 0 and 1
+ *                    of block i-1;
  *       substream 2: the walker's start, blocks 0 and 1;
  *   - a word w maps to the uniform deviate (w + 1/2) 2^-32, exact in FP64;
  *   - the volume is periodic; displacements are unwrapped;
@@ -292,21 +295,22 @@ static int walk_step(const rmso_geom* g, rmso_walker* w, const double v_in[3], m
     }
 }
 
-/* Membrane words of step i drawn lazily from substream 1. */
+/* Membrane words of step i (index = i - 1): the first from substream 1, the
+ * second and third from substream 3. */
 typedef struct {
     uint64_t seed, walker;
     uint32_t index;
-    int have;
-    uint32_t words[4];
 } philox_mw_ctx;
 
 static uint32_t philox_mw(void* p, int k) {
-    philox_mw_ctx* c = (philox_mw_ctx*)p;
-    if (!c->have) {
-        philox_block(c->seed, c->index, 1u, c->walker, c->words);
-        c->have = 1;
+    const philox_mw_ctx* c = (const philox_mw_ctx*)p;
+    uint32_t w[4];
+    if (k == 0) {
+        philox_block(c->seed, c->index / 4u, 1u, c->walker, w);
+        return w[c->index % 4u];
     }
-    return c->words[k];
+    philox_block(c->seed, c->index, 3u, c->walker, w);
+    return w[k - 1];
 }
 
 /* Words handed in by a unit test. */
@@ -401,7 +405,7 @@ static void walk_one(run_ctx* c, int64_t slot) {
         const int h = (int)((i - 1) & 1);
         double v[3];
         rmso_direction(dirw[2 * h], dirw[2 * h + 1], v);
-        philox_mw_ctx mc = {c->seed, wid, (uint32_t)(i - 1), 0, {0, 0, 0, 0}};
+        philox_mw_ctx mc = {c->seed, wid, (uint32_t)(i - 1)};
         const int r = walk_step(&c->g, &w, v, philox_mw, &mc);
         if (r < 0) {
             atomic_store(&c->err, r);

@@ -25,8 +25,11 @@
 // Random numbers: Philox4x32-10 (Salmon et al., SC'11) keyed by the 64-bit
 // seed with counter (index, substream, walker_lo, walker_hi): substream 0
 // block j gives the directions of steps 2j+1 (words 0, 1) and 2j+2 (words 2,
-// 3); substream 1 block i-1 the membrane words of step i, in order of use;
-// substream 2 blocks 0 and 1 the start.  A walker's trajectory therefore
+// 3); the first membrane word of step i is word (i-1) mod 4 of substream 1
+// block (i-1)/4 (computed for the whole wave once per four steps, since some
+// lane of a wave meets a membrane in most steps); the rare second and third
+// membrane words of a step are words 0 and 1 of substream 3 block i-1;
+// substream 2 blocks 0 and 1 give the start.  A walker's trajectory therefore
 // depends only on (seed, walker index, step index), and a walk can stop after
 // any step and resume from its stored state with identical results.
 //
@@ -213,7 +216,8 @@ struct WalkerF64 {
 
     // One step (index i0 = i - 1) with direction words wa, wb.
     __device__ __forceinline__ void step(const WalkPlan& p, const LabelT* __restrict__ lab,
-                                         uint32_t i0, uint32_t wa, uint32_t wb, const Ids& id) {
+                                         uint32_t i0, uint32_t wa, uint32_t wb, uint32_t m1,
+                                         const Ids& id) {
         const double u1 = unit_open(wa);
         const double u2 = unit_open(wb);
         double sn, cs;
@@ -257,8 +261,8 @@ struct WalkerF64 {
                 bool cross = true;
                 if (nl != l) {
                     ++nhit;
-                    if (mw_used == 0) mw = philox4x32_10(i0, 1u, id.wlo, id.whi, id.k0, id.k1);
-                    const uint32_t word = mw_used == 0 ? mw.x : (mw_used == 1 ? mw.y : mw.z);
+                    if (mw_used == 1) mw = philox4x32_10(i0, 3u, id.wlo, id.whi, id.k0, id.k1);
+                    const uint32_t word = mw_used == 0 ? m1 : (mw_used == 1 ? mw.x : mw.y);
                     ++mw_used;
                     cross = word < p.thr[l * p.n_labels + nl];
                     if (cross) {
@@ -377,7 +381,8 @@ struct WalkerMixed {
     }
 
     __device__ __forceinline__ void step(const WalkPlan& p, const LabelT* __restrict__ lab,
-                                         uint32_t i0, uint32_t wa, uint32_t wb, const Ids& id) {
+                                         uint32_t i0, uint32_t wa, uint32_t wb, uint32_t m1,
+                                         const Ids& id) {
         const double u1d = unit_open(wa);
         const float u1 = static_cast<float>(u1d);
         const float u2 = unit_open_f(wb);
@@ -420,8 +425,8 @@ struct WalkerMixed {
                 bool cross = true;
                 if (nl != l) {
                     ++nhit;
-                    if (mw_used == 0) mw = philox4x32_10(i0, 1u, id.wlo, id.whi, id.k0, id.k1);
-                    const uint32_t word = mw_used == 0 ? mw.x : (mw_used == 1 ? mw.y : mw.z);
+                    if (mw_used == 1) mw = philox4x32_10(i0, 3u, id.wlo, id.whi, id.k0, id.k1);
+                    const uint32_t word = mw_used == 0 ? m1 : (mw_used == 1 ? mw.x : mw.y);
                     ++mw_used;
                     cross = word < p.thr[l * p.n_labels + nl];
                     if (cross) {
@@ -496,15 +501,19 @@ struct WalkerMixed {
     }
 };
 
-// Steps [b, e) of one walker.  Direction words come two steps per Philox block.
+// Steps [b, e) of one walker: direction words two steps per Philox block,
+// first membrane words four steps per block.
 template <class Walker, typename LabelT>
 __device__ __forceinline__ void walk_range(const WalkPlan& p, const LabelT* __restrict__ lab,
                                            Walker& W, uint32_t b, uint32_t e, const Ids& id) {
-    uint4 wd = make_uint4(0, 0, 0, 0);
+    uint4 wd = make_uint4(0, 0, 0, 0), wm = make_uint4(0, 0, 0, 0);
     for (uint32_t i0 = b; i0 < e; ++i0) {
         const bool odd = (i0 & 1u) != 0;
         if (!odd || i0 == b) wd = philox4x32_10(i0 >> 1, 0u, id.wlo, id.whi, id.k0, id.k1);
-        W.step(p, lab, i0, odd ? wd.z : wd.x, odd ? wd.w : wd.y, id);
+        const uint32_t q = i0 & 3u;
+        if (q == 0 || i0 == b) wm = philox4x32_10(i0 >> 2, 1u, id.wlo, id.whi, id.k0, id.k1);
+        const uint32_t m1 = q == 0 ? wm.x : (q == 1 ? wm.y : (q == 2 ? wm.z : wm.w));
+        W.step(p, lab, i0, odd ? wd.z : wd.x, odd ? wd.w : wd.y, m1, id);
     }
 }
 
