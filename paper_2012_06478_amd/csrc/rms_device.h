@@ -187,7 +187,7 @@ __device__ __forceinline__ Start draw_start(const WalkPlan& p, const Ids& id) {
 template <typename LabelT, int NS>
 struct WalkerF64 {
     static constexpr int kShapes = NS > 0 ? NS : 1;
-    int ix, iy, iz, l, l0;
+    int ix, iy, iz, lin, l, l0;  // voxel coordinates, linear voxel index, labels
     uint32_t nface, nhit, nperm;
     double o[3];
     double sig, it2;
@@ -201,6 +201,7 @@ struct WalkerF64 {
         ix = s.ix;
         iy = s.iy;
         iz = s.iz;
+        lin = static_cast<int>(s.lin);
         o[0] = unit_open(s.wox);
         o[1] = unit_open(s.woy);
         o[2] = unit_open(s.woz);
@@ -214,7 +215,8 @@ struct WalkerF64 {
         nface = nhit = nperm = 0;
     }
 
-    // One step (index i0 = i - 1) with direction words wa, wb.
+    // One step (index i0 = i - 1) with direction words wa, wb and first
+    // membrane word m1.
     __device__ __forceinline__ void step(const WalkPlan& p, const LabelT* __restrict__ lab,
                                          uint32_t i0, uint32_t wa, uint32_t wb, uint32_t m1,
                                          const Ids& id) {
@@ -225,13 +227,24 @@ struct WalkerF64 {
         const double rho = 2.0 * sqrt_pos(u1 * (1.0 - u1));
         const double v[3] = {rho * cs, rho * sn, 1.0 - 2.0 * u1};
 
-        // path length to the face each axis moves toward
+        // Per axis: the path length to the face the step moves toward, and the
+        // (periodic) neighbour voxel across that face.
+        const int c[3] = {ix, iy, iz};
+        const int n[3] = {p.nx, p.ny, p.nz};
+        const int st[3] = {1, p.nx, p.nx * p.ny};
         double e[3];
+        int nb[3];
+        uint32_t posm = 0;
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
+            const bool pos = v[a] > 0.0;
+            posm |= pos ? (1u << a) : 0u;
             const double av = fabs(v[a]);
-            const double gap = fmax(v[a] > 0.0 ? 1.0 - o[a] : o[a], 0.0);
+            const double gap = fmax(pos ? 1.0 - o[a] : o[a], 0.0);
             e[a] = av > 0.0 ? gap * recip_pos(av) : INFINITY;
+            const int wrap = n[a] * st[a];
+            nb[a] = lin + (pos ? (c[a] == n[a] - 1 ? st[a] - wrap : st[a])
+                               : (c[a] == 0 ? wrap - st[a] : -st[a]));
         }
         // stable sort of (e, axis): ties keep x < y < z
         double s0 = e[0], s1 = e[1], s2 = e[2];
@@ -252,12 +265,8 @@ struct WalkerF64 {
             go = go && (ek < pend);
             if (go) {
                 ++nface;
-                const double va = a == 0 ? v[0] : (a == 1 ? v[1] : v[2]);
-                const int sgn = va > 0.0 ? 1 : -1;
-                const int cx = a == 0 ? wrap_step(ix, sgn, p.nx) : ix;
-                const int cy = a == 1 ? wrap_step(iy, sgn, p.ny) : iy;
-                const int cz = a == 2 ? wrap_step(iz, sgn, p.nz) : iz;
-                const int nl = lab[cx + p.nx * (cy + p.ny * cz)];
+                const int nbk = a == 0 ? nb[0] : (a == 1 ? nb[1] : nb[2]);
+                const int nl = lab[nbk];
                 bool cross = true;
                 if (nl != l) {
                     ++nhit;
@@ -278,10 +287,17 @@ struct WalkerF64 {
                     }
                 }
                 if (cross) {
+                    // into the neighbour: the other axes' neighbours shift with it
                     passed |= 1u << a;
-                    ix = cx;
-                    iy = cy;
-                    iz = cz;
+                    const int dl = nbk - lin;
+                    lin = nbk;
+                    nb[0] += dl;
+                    nb[1] += dl;
+                    nb[2] += dl;
+                    const int da = (posm >> a) & 1u ? 1 : -1;
+                    if (a == 0) ix = wrap_step(ix, da, p.nx);
+                    else if (a == 1) iy = wrap_step(iy, da, p.ny);
+                    else iz = wrap_step(iz, da, p.nz);
                 } else {
                     refl |= 1u << a;
                 }
@@ -289,18 +305,22 @@ struct WalkerF64 {
         }
         const double lend = fma(tau, sig, P);
         R = fma(p.dt * tau, it2, R);
+        // End point per axis from the free end point o + lend v: mirrored about
+        // the face after a reflection, shifted by one voxel after a pass.
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            const bool pos = v[a] > 0.0;
-            const double rest = (lend - e[a]) * v[a];  // signed travel after the face
-            double on;
-            if (refl & (1u << a)) on = (pos ? 1.0 : 0.0) - rest;
-            else if (passed & (1u << a)) on = (pos ? 0.0 : 1.0) + rest;
-            else on = fma(lend, v[a], o[a]);
-            on = fmin(fmax(on, 0.0), 1.0);
-            const double shift = (passed & (1u << a)) ? (pos ? 1.0 : -1.0) : 0.0;
-            d[a] += (on - o[a]) + shift;
-            o[a] = on;
+            const bool pos = (posm >> a) & 1u;
+            const double fr = fma(lend, v[a], o[a]);
+            double on, dd;
+            if (refl & (1u << a)) {
+                on = (pos ? 2.0 : 0.0) - fr;
+                dd = on - o[a];
+            } else {
+                on = (passed & (1u << a)) ? fr - (pos ? 1.0 : -1.0) : fr;
+                dd = lend * v[a];
+            }
+            d[a] += dd;
+            o[a] = fmin(fmax(on, 0.0), 1.0);
         }
 #pragma unroll
         for (int q = 0; q < NS; ++q) {
