@@ -103,6 +103,15 @@ int build_tables(const rms_substrate& sub, const double* D, const double* kappa,
     return RMS_OK;
 }
 
+// Multiplier and shift for exact division of n < 2^31 by d >= 1:
+// n / d == (n m) >> sh with sh = 31 + ceil(log2 d), m = ceil(2^sh / d) < 2^32.
+void div_magic(uint32_t d, uint32_t* m, uint32_t* sh) {
+    uint32_t s = 0;
+    while ((uint64_t(1) << s) < d) ++s;
+    *sh = 31 + s;
+    *m = static_cast<uint32_t>(((uint64_t(1) << *sh) + d - 1) / d);
+}
+
 template <typename T>
 hipError_t dev_alloc(DeviceRun& d, T** p, size_t count) {
     void* q = nullptr;
@@ -286,6 +295,8 @@ int DeviceRun::create(const rms_substrate& sub, const RunSetup& r, bool resumabl
     wp.nx = static_cast<int>(sub.dims[0]);
     wp.ny = static_cast<int>(sub.dims[1]);
     wp.nz = static_cast<int>(sub.dims[2]);
+    div_magic(static_cast<uint32_t>(sub.dims[0]), &wp.div_nx_m, &wp.div_nx_sh);
+    div_magic(static_cast<uint32_t>(sub.dims[0] * sub.dims[1]), &wp.div_nxy_m, &wp.div_nxy_sh);
     wp.allowed = sub.d_allowed;
     wp.n_allowed = sub.n_allowed;
     wp.n_labels = sub.n_labels;

@@ -36,7 +36,8 @@
 // Mixed form: the position is an exact int32 voxel index plus an fp32 offset,
 // so a coordinate keeps the same absolute precision anywhere in the volume
 // (the point of taking voxel membership from the integer part, section
-// 2.1.1).  Directions use the hardware sine and cosine (argument in
+// 2.1.1).  Directions take u1, u2 from the top 24 bits of the same words and
+// use the hardware sine and cosine (argument in
 // revolutions, so 2 pi u needs no range reduction); face distances, end points
 // and budgets are fp32; the displacement is the exact count of voxels crossed
 // plus the fp32 offset change; the phase and R are Neumaier-compensated fp32
@@ -49,14 +50,20 @@
 namespace rms {
 namespace dev {
 
+// a ^ b ^ c in one instruction (gfx950 three-input bit operation, truth
+// table 0x96 over the operand patterns 0xF0, 0xCC, 0xAA)
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+}
+
 __device__ __forceinline__ uint4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2,
                                                uint32_t c3, uint32_t k0, uint32_t k1) {
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
         const uint64_t p0 = static_cast<uint64_t>(0xD2511F53u) * c0;
         const uint64_t p1 = static_cast<uint64_t>(0xCD9E8D57u) * c2;
-        const uint32_t n0 = static_cast<uint32_t>(p1 >> 32) ^ c1 ^ k0;
-        const uint32_t n2 = static_cast<uint32_t>(p0 >> 32) ^ c3 ^ k1;
+        const uint32_t n0 = xor3(static_cast<uint32_t>(p1 >> 32), c1, k0);
+        const uint32_t n2 = xor3(static_cast<uint32_t>(p0 >> 32), c3, k1);
         c1 = static_cast<uint32_t>(p1);
         c3 = static_cast<uint32_t>(p0);
         c0 = n0;
@@ -78,36 +85,49 @@ __device__ __forceinline__ int wrap_step(int c, int d, int n) {
     return c >= n ? c - n : c;
 }
 
+// fma(a, b, k) with the constant k taken from a scalar register pair: written
+// as the three-operand instruction so the compiler does not keep the
+// polynomial coefficients in vector registers and copy one before every
+// accumulate.
+struct FmaSgpr {
+    __device__ __forceinline__ double operator()(double a, double b, double k) const {
+        double d;
+        asm("v_fma_f64 %0, %1, %2, %3" : "=v"(d) : "v"(a), "v"(b), "s"(k));
+        return d;
+    }
+};
+
 // cos(2 pi u) and sin(2 pi u) for u in [0, 1] to about 1 ulp.  Reduction to a
 // quarter turn is exact: x = 4u, k = rint(x), r = x - k in [-1/2, 1/2], so
 // 2 pi u = k pi/2 + a with a = r pi/2, |a| <= pi/4.  sin a and cos a are the
 // Taylor series of sine and cosine through a^17 and a^18 (the next terms are
 // below 1e-19 on |a| <= pi/4), evaluated by Horner's rule in a^2; the quadrant
-// k mod 4 then permutes and negates them.
-__host__ __device__ __forceinline__ void sincos_2pi(double u, double* s_out, double* c_out) {
+// k mod 4 then permutes and negates them.  `fk` is the fused multiply-add used
+// for the Horner steps (its third operand is a coefficient).
+template <class Fma>
+__host__ __device__ __forceinline__ void sincos_2pi(double u, double* s_out, double* c_out,
+                                                    Fma fk) {
     const double x = 4.0 * u;
     const double k = rint(x);
     const double a = (x - k) * 1.5707963267948966;  // pi/2
     const double z = a * a;
     // sin a = a sum_k (-1)^k z^k / (2k+1)!,  k = 0..8
-    double ps = 1.0 / 355687428096000.0;              // 1/17!
-    ps = fma(z, ps, -1.0 / 1307674368000.0);          // 1/15!
-    ps = fma(z, ps, 1.0 / 6227020800.0);              // 1/13!
-    ps = fma(z, ps, -1.0 / 39916800.0);               // 1/11!
-    ps = fma(z, ps, 1.0 / 362880.0);                  // 1/9!
-    ps = fma(z, ps, -1.0 / 5040.0);                   // 1/7!
-    ps = fma(z, ps, 1.0 / 120.0);                     // 1/5!
-    ps = fma(z, ps, -1.0 / 6.0);                      // 1/3!
+    double ps = fk(z, 1.0 / 355687428096000.0, -1.0 / 1307674368000.0);  // 1/17!, 1/15!
+    ps = fk(z, ps, 1.0 / 6227020800.0);               // 1/13!
+    ps = fk(z, ps, -1.0 / 39916800.0);                // 1/11!
+    ps = fk(z, ps, 1.0 / 362880.0);                   // 1/9!
+    ps = fk(z, ps, -1.0 / 5040.0);                    // 1/7!
+    ps = fk(z, ps, 1.0 / 120.0);                      // 1/5!
+    ps = fk(z, ps, -1.0 / 6.0);                       // 1/3!
     const double sa = fma(a * z, ps, a);
     // cos a = sum_k (-1)^k z^k / (2k)!,  k = 0..9
-    double pc = -1.0 / 6402373705728000.0;            // 1/18!
-    pc = fma(z, pc, 1.0 / 20922789888000.0);          // 1/16!
-    pc = fma(z, pc, -1.0 / 87178291200.0);            // 1/14!
-    pc = fma(z, pc, 1.0 / 479001600.0);               // 1/12!
-    pc = fma(z, pc, -1.0 / 3628800.0);                // 1/10!
-    pc = fma(z, pc, 1.0 / 40320.0);                   // 1/8!
-    pc = fma(z, pc, -1.0 / 720.0);                    // 1/6!
-    pc = fma(z, pc, 1.0 / 24.0);                      // 1/4!
+    double pc = fk(z, -1.0 / 6402373705728000.0, 1.0 / 20922789888000.0);  // 1/18!, 1/16!
+    pc = fk(z, pc, -1.0 / 87178291200.0);             // 1/14!
+    pc = fk(z, pc, 1.0 / 479001600.0);                // 1/12!
+    pc = fk(z, pc, -1.0 / 3628800.0);                 // 1/10!
+    pc = fk(z, pc, 1.0 / 40320.0);                    // 1/8!
+    pc = fk(z, pc, -1.0 / 720.0);                     // 1/6!
+    pc = fk(z, pc, 1.0 / 24.0);                       // 1/4!
     pc = fma(z, pc, -0.5);                            // 1/2!
     const double ca = fma(z, pc, 1.0);
     const int q = static_cast<int>(k) & 3;
@@ -154,11 +174,50 @@ struct Ids {
     uint32_t wlo, whi, k0, k1;
 };
 
+// n / d for n < 2^31 as (n m) >> sh with m = ceil(2^sh / d), sh = 31 +
+// ceil(log2 d): exact, because the error n (m - 2^sh/d) / 2^sh stays below
+// 2^-ceil(log2 d) <= 1/d.  m and sh come from the host.
+__device__ __forceinline__ uint32_t div_magic(uint32_t n, uint32_t m, uint32_t sh) {
+    return static_cast<uint32_t>((static_cast<uint64_t>(n) * m) >> sh);
+}
+
+struct Coords {
+    int c[3];
+};
+
+__device__ __forceinline__ Coords coords_of(const WalkPlan& p, int lin) {
+    const uint32_t nxy = static_cast<uint32_t>(p.nx) * static_cast<uint32_t>(p.ny);
+    const uint32_t z = div_magic(static_cast<uint32_t>(lin), p.div_nxy_m, p.div_nxy_sh);
+    const uint32_t r = static_cast<uint32_t>(lin) - z * nxy;
+    const uint32_t y = div_magic(r, p.div_nx_m, p.div_nx_sh);
+    Coords k;
+    k.c[0] = static_cast<int>(r - y * static_cast<uint32_t>(p.nx));
+    k.c[1] = static_cast<int>(y);
+    k.c[2] = static_cast<int>(z);
+    return k;
+}
+
+// Linear index of the voxel across the face each axis moves toward (bit a of
+// posm set: toward +a), with periodic wrap.  Every result lies in
+// [0, nx ny nz) because it steps one voxel along an axis from a valid voxel,
+// or jumps to the opposite end of that axis at its edge.
+__device__ __forceinline__ void neighbours(const WalkPlan& p, int lin, uint32_t posm, int nb[3]) {
+    const Coords k = coords_of(p, lin);
+    const int n[3] = {p.nx, p.ny, p.nz};
+    const int st[3] = {1, p.nx, p.nx * p.ny};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const bool pos = (posm >> a) & 1u;
+        const int edge = pos ? n[a] - 1 : 0;  // the coordinate at which the step wraps
+        const int mag = k.c[a] == edge ? st[a] - n[a] * st[a] : st[a];
+        nb[a] = lin + (pos ? mag : -mag);
+    }
+}
+
 // Start (section 2.2, item 1): uniform over the voxels that are not dead, then
 // uniform inside the voxel.
 struct Start {
-    int ix, iy, iz;
-    uint32_t lin;
+    int lin;
     uint32_t wox, woy, woz;  // offset words
 };
 
@@ -169,16 +228,35 @@ __device__ __forceinline__ Start draw_start(const WalkPlan& p, const Ids& id) {
     const uint32_t rank =
         static_cast<uint32_t>(__umul64hi(r64, static_cast<uint64_t>(p.n_allowed)));
     Start s;
-    s.lin = p.allowed ? p.allowed[rank] : rank;
-    const uint32_t nxy = static_cast<uint32_t>(p.nx) * static_cast<uint32_t>(p.ny);
-    s.iz = static_cast<int>(s.lin / nxy);
-    const uint32_t rem = s.lin - static_cast<uint32_t>(s.iz) * nxy;
-    s.iy = static_cast<int>(rem / static_cast<uint32_t>(p.nx));
-    s.ix = static_cast<int>(rem - static_cast<uint32_t>(s.iy) * static_cast<uint32_t>(p.nx));
+    s.lin = static_cast<int>(p.allowed ? p.allowed[rank] : rank);
     s.wox = b0.z;
     s.woy = b0.w;
     s.woz = b1.x;
     return s;
+}
+
+// Order of the three face events of a step: a stable sort of (distance, axis),
+// ties keep x < y < z.
+template <typename Real>
+__device__ __forceinline__ void sort3(const Real e[3], Real s[3], int ax[3]) {
+    s[0] = e[0];
+    s[1] = e[1];
+    s[2] = e[2];
+    ax[0] = 0;
+    ax[1] = 1;
+    ax[2] = 2;
+    auto cswap = [&](int i, int j) {  // compare-exchange as selects, no branches
+        const bool c = s[j] < s[i];
+        const Real lo = c ? s[j] : s[i], hi = c ? s[i] : s[j];
+        const int alo = c ? ax[j] : ax[i], ahi = c ? ax[i] : ax[j];
+        s[i] = lo;
+        s[j] = hi;
+        ax[i] = alo;
+        ax[j] = ahi;
+    };
+    cswap(0, 1);
+    cswap(1, 2);
+    cswap(0, 1);
 }
 
 // ---------------------------------------------------------------------------
@@ -187,7 +265,7 @@ __device__ __forceinline__ Start draw_start(const WalkPlan& p, const Ids& id) {
 template <typename LabelT, int NS>
 struct WalkerF64 {
     static constexpr int kShapes = NS > 0 ? NS : 1;
-    int ix, iy, iz, lin, l, l0;  // voxel coordinates, linear voxel index, labels
+    int lin, l, l0;  // linear voxel index, label, label at the start
     uint32_t nface, nhit, nperm;
     double o[3];
     double sig, it2;
@@ -198,10 +276,7 @@ struct WalkerF64 {
     __device__ __forceinline__ void init(const WalkPlan& p, const LabelT* __restrict__ lab,
                                          const Ids& id) {
         const Start s = draw_start(p, id);
-        ix = s.ix;
-        iy = s.iy;
-        iz = s.iz;
-        lin = static_cast<int>(s.lin);
+        lin = s.lin;
         o[0] = unit_open(s.wox);
         o[1] = unit_open(s.woy);
         o[2] = unit_open(s.woz);
@@ -223,17 +298,12 @@ struct WalkerF64 {
         const double u1 = unit_open(wa);
         const double u2 = unit_open(wb);
         double sn, cs;
-        sincos_2pi(u2, &sn, &cs);
+        sincos_2pi(u2, &sn, &cs, FmaSgpr());
         const double rho = 2.0 * sqrt_pos(u1 * (1.0 - u1));
         const double v[3] = {rho * cs, rho * sn, 1.0 - 2.0 * u1};
 
-        // Per axis: the path length to the face the step moves toward, and the
-        // (periodic) neighbour voxel across that face.
-        const int c[3] = {ix, iy, iz};
-        const int n[3] = {p.nx, p.ny, p.nz};
-        const int st[3] = {1, p.nx, p.nx * p.ny};
+        // per axis: path length to the face the step moves toward
         double e[3];
-        int nb[3];
         uint32_t posm = 0;
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
@@ -242,16 +312,12 @@ struct WalkerF64 {
             const double av = fabs(v[a]);
             const double gap = fmax(pos ? 1.0 - o[a] : o[a], 0.0);
             e[a] = av > 0.0 ? gap * recip_pos(av) : INFINITY;
-            const int wrap = n[a] * st[a];
-            nb[a] = lin + (pos ? (c[a] == n[a] - 1 ? st[a] - wrap : st[a])
-                               : (c[a] == 0 ? wrap - st[a] : -st[a]));
         }
-        // stable sort of (e, axis): ties keep x < y < z
-        double s0 = e[0], s1 = e[1], s2 = e[2];
-        int a0 = 0, a1 = 1, a2 = 2;
-        if (s1 < s0) { const double t = s0; s0 = s1; s1 = t; const int q = a0; a0 = a1; a1 = q; }
-        if (s2 < s1) { const double t = s1; s1 = s2; s2 = t; const int q = a1; a1 = a2; a2 = q; }
-        if (s1 < s0) { const double t = s0; s0 = s1; s1 = t; const int q = a0; a0 = a1; a1 = q; }
+        int nb[3];
+        neighbours(p, lin, posm, nb);
+        double se[3];
+        int ax[3];
+        sort3(e, se, ax);
 
         double P = 0.0, tau = 1.0, pend = sig;
         uint32_t passed = 0, refl = 0;
@@ -260,8 +326,8 @@ struct WalkerF64 {
         bool go = true;
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-            const double ek = k == 0 ? s0 : (k == 1 ? s1 : s2);
-            const int a = k == 0 ? a0 : (k == 1 ? a1 : a2);
+            const double ek = se[k];
+            const int a = ax[k];
             go = go && (ek < pend);
             if (go) {
                 ++nface;
@@ -294,10 +360,6 @@ struct WalkerF64 {
                     nb[0] += dl;
                     nb[1] += dl;
                     nb[2] += dl;
-                    const int da = (posm >> a) & 1u ? 1 : -1;
-                    if (a == 0) ix = wrap_step(ix, da, p.nx);
-                    else if (a == 1) iy = wrap_step(iy, da, p.ny);
-                    else iz = wrap_step(iz, da, p.nz);
                 } else {
                     refl |= 1u << a;
                 }
@@ -310,16 +372,11 @@ struct WalkerF64 {
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
             const bool pos = (posm >> a) & 1u;
+            const bool rf = (refl >> a) & 1u;
             const double fr = fma(lend, v[a], o[a]);
-            double on, dd;
-            if (refl & (1u << a)) {
-                on = (pos ? 2.0 : 0.0) - fr;
-                dd = on - o[a];
-            } else {
-                on = (passed & (1u << a)) ? fr - (pos ? 1.0 : -1.0) : fr;
-                dd = lend * v[a];
-            }
-            d[a] += dd;
+            const double mirror = (pos ? 2.0 : 0.0) - fr;
+            const double on = rf ? mirror : ((passed >> a) & 1u ? fr - (pos ? 1.0 : -1.0) : fr);
+            d[a] += rf ? mirror - o[a] : lend * v[a];
             o[a] = fmin(fmax(on, 0.0), 1.0);
         }
 #pragma unroll
@@ -335,14 +392,15 @@ struct WalkerF64 {
 
     // Per-walker record (layout of RMS_DUMP_WIDTH in rms.h).
     __device__ __forceinline__ void finish(const WalkPlan& p, double* out) const {
+        const Coords k = coords_of(p, lin);
         out[0] = d[0] * p.voxel_um;
         out[1] = d[1] * p.voxel_um;
         out[2] = d[2] * p.voxel_um;
         out[3] = R;
         out[4] = l;
-        out[5] = ix;
-        out[6] = iy;
-        out[7] = iz;
+        out[5] = k.c[0];
+        out[6] = k.c[1];
+        out[7] = k.c[2];
         out[8] = o[0];
         out[9] = o[1];
         out[10] = o[2];
@@ -370,7 +428,7 @@ __device__ __forceinline__ float unit_open_f(uint32_t w) {
 template <typename LabelT, int NS>
 struct WalkerMixed {
     static constexpr int kShapes = NS > 0 ? NS : 1;
-    int ix, iy, iz, l, l0;
+    int lin, l, l0;
     uint32_t nface, nhit, nperm;
     int n[3];     // voxels crossed per axis (signed), exact
     float o[3];   // offset in the voxel, [0, 1]
@@ -382,9 +440,7 @@ struct WalkerMixed {
     __device__ __forceinline__ void init(const WalkPlan& p, const LabelT* __restrict__ lab,
                                          const Ids& id) {
         const Start s = draw_start(p, id);
-        ix = s.ix;
-        iy = s.iy;
-        iz = s.iz;
+        lin = s.lin;
         o[0] = o0[0] = unit_open_f(s.wox);
         o[1] = o0[1] = unit_open_f(s.woy);
         o[2] = o0[2] = unit_open_f(s.woz);
@@ -403,26 +459,29 @@ struct WalkerMixed {
     __device__ __forceinline__ void step(const WalkPlan& p, const LabelT* __restrict__ lab,
                                          uint32_t i0, uint32_t wa, uint32_t wb, uint32_t m1,
                                          const Ids& id) {
-        const double u1d = unit_open(wa);
-        const float u1 = static_cast<float>(u1d);
-        const float u2 = unit_open_f(wb);
+        // uniform deviates from the top 24 bits of each word: (k + 1/2) 2^-24
+        const float u1 = fmaf(static_cast<float>(wa >> 8), 0x1p-24f, 0x1p-25f);
+        const float u2 = fmaf(static_cast<float>(wb >> 8), 0x1p-24f, 0x1p-25f);
         const float cs = __builtin_amdgcn_cosf(u2);  // cos(2 pi u2)
         const float sn = __builtin_amdgcn_sinf(u2);  // sin(2 pi u2)
         const float rho = 2.0f * __builtin_sqrtf(u1 * (1.0f - u1));
-        const float v[3] = {rho * cs, rho * sn, static_cast<float>(1.0 - 2.0 * u1d)};
+        const float v[3] = {rho * cs, rho * sn, fmaf(-2.0f, u1, 1.0f)};
 
         float e[3];
+        uint32_t posm = 0;
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
+            const bool pos = v[a] > 0.0f;
+            posm |= pos ? (1u << a) : 0u;
             const float av = fabsf(v[a]);
-            const float gap = fmaxf(v[a] > 0.0f ? 1.0f - o[a] : o[a], 0.0f);
+            const float gap = fmaxf(pos ? 1.0f - o[a] : o[a], 0.0f);
             e[a] = av > 0.0f ? gap * __builtin_amdgcn_rcpf(av) : INFINITY;
         }
-        float s0 = e[0], s1 = e[1], s2 = e[2];
-        int a0 = 0, a1 = 1, a2 = 2;
-        if (s1 < s0) { const float t = s0; s0 = s1; s1 = t; const int q = a0; a0 = a1; a1 = q; }
-        if (s2 < s1) { const float t = s1; s1 = s2; s2 = t; const int q = a1; a1 = a2; a2 = q; }
-        if (s1 < s0) { const float t = s0; s0 = s1; s1 = t; const int q = a0; a0 = a1; a1 = q; }
+        int nb[3];
+        neighbours(p, lin, posm, nb);
+        float se[3];
+        int ax[3];
+        sort3(e, se, ax);
 
         float P = 0.0f, tau = 1.0f, pend = sig;
         uint32_t passed = 0, refl = 0;
@@ -431,17 +490,13 @@ struct WalkerMixed {
         bool go = true;
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-            const float ek = k == 0 ? s0 : (k == 1 ? s1 : s2);
-            const int a = k == 0 ? a0 : (k == 1 ? a1 : a2);
+            const float ek = se[k];
+            const int a = ax[k];
             go = go && (ek < pend);
             if (go) {
                 ++nface;
-                const float va = a == 0 ? v[0] : (a == 1 ? v[1] : v[2]);
-                const int sgn = va > 0.0f ? 1 : -1;
-                const int cx = a == 0 ? wrap_step(ix, sgn, p.nx) : ix;
-                const int cy = a == 1 ? wrap_step(iy, sgn, p.ny) : iy;
-                const int cz = a == 2 ? wrap_step(iz, sgn, p.nz) : iz;
-                const int nl = lab[cx + p.nx * (cy + p.ny * cz)];
+                const int nbk = a == 0 ? nb[0] : (a == 1 ? nb[1] : nb[2]);
+                const int nl = lab[nbk];
                 bool cross = true;
                 if (nl != l) {
                     ++nhit;
@@ -463,9 +518,11 @@ struct WalkerMixed {
                 }
                 if (cross) {
                     passed |= 1u << a;
-                    ix = cx;
-                    iy = cy;
-                    iz = cz;
+                    const int dl = nbk - lin;
+                    lin = nbk;
+                    nb[0] += dl;
+                    nb[1] += dl;
+                    nb[2] += dl;
                 } else {
                     refl |= 1u << a;
                 }
@@ -475,14 +532,13 @@ struct WalkerMixed {
         nsum(R, Rc, static_cast<float>(p.dt) * tau * it2);
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            const bool pos = v[a] > 0.0f;
-            const float rest = (lend - e[a]) * v[a];
-            float on;
-            if (refl & (1u << a)) on = (pos ? 1.0f : 0.0f) - rest;
-            else if (passed & (1u << a)) on = (pos ? 0.0f : 1.0f) + rest;
-            else on = fmaf(lend, v[a], o[a]);
+            const bool pos = (posm >> a) & 1u;
+            const bool rf = (refl >> a) & 1u;
+            const bool ps = (passed >> a) & 1u;
+            const float fr = fmaf(lend, v[a], o[a]);
+            const float on = rf ? (pos ? 2.0f : 0.0f) - fr : (ps ? fr - (pos ? 1.0f : -1.0f) : fr);
             o[a] = fminf(fmaxf(on, 0.0f), 1.0f);
-            if (passed & (1u << a)) n[a] += pos ? 1 : -1;
+            n[a] += ps ? (pos ? 1 : -1) : 0;
         }
 #pragma unroll
         for (int q = 0; q < NS; ++q) {
@@ -496,15 +552,16 @@ struct WalkerMixed {
     }
 
     __device__ __forceinline__ void finish(const WalkPlan& p, double* out) const {
+        const Coords k = coords_of(p, lin);
 #pragma unroll
         for (int a = 0; a < 3; ++a)
             out[a] = (static_cast<double>(n[a]) +
                       (static_cast<double>(o[a]) - static_cast<double>(o0[a]))) * p.voxel_um;
         out[3] = static_cast<double>(R) + static_cast<double>(Rc);
         out[4] = l;
-        out[5] = ix;
-        out[6] = iy;
-        out[7] = iz;
+        out[5] = k.c[0];
+        out[6] = k.c[1];
+        out[7] = k.c[2];
         out[8] = o[0];
         out[9] = o[1];
         out[10] = o[2];
@@ -522,7 +579,9 @@ struct WalkerMixed {
 };
 
 // Steps [b, e) of one walker: direction words two steps per Philox block,
-// first membrane words four steps per block.
+// first membrane words four steps per block (both blocks computed under
+// wave-uniform branches).  One step per iteration keeps consecutive steps
+// from being interleaved by the scheduler, which would raise register use.
 template <class Walker, typename LabelT>
 __device__ __forceinline__ void walk_range(const WalkPlan& p, const LabelT* __restrict__ lab,
                                            Walker& W, uint32_t b, uint32_t e, const Ids& id) {

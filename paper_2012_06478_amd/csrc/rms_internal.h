@@ -16,6 +16,8 @@ struct WalkPlan {
     const void* labels;  // nx*ny*nz labels, x fastest (uint8 or uint16)
     int label_bytes;
     int nx, ny, nz;
+    uint32_t div_nx_m, div_nx_sh;    // n / nx == (n div_nx_m) >> div_nx_sh for n < 2^31
+    uint32_t div_nxy_m, div_nxy_sh;  // n / (nx ny), likewise
     const uint32_t* allowed;  // ascending linear indices of non-dead voxels, or null (all)
     uint32_t n_allowed;
     int n_labels;

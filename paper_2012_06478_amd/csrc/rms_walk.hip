@@ -20,8 +20,13 @@ namespace {
 
 using dev::Ids;
 
+// Five waves per SIMD: the double-precision walker then fits 96 registers
+// (a few bytes of spill outside the step) and runs about 7% faster than at
+// four; the mixed walker needs fewer registers and is not affected.
+#define RMS_WALK_OCCUPANCY __attribute__((amdgpu_waves_per_eu(5, 8)))
+
 template <class Walker, typename LabelT>
-__global__ __launch_bounds__(kBlock) void walk_kernel(WalkPlan p) {
+__global__ __launch_bounds__(kBlock) RMS_WALK_OCCUPANCY void walk_kernel(WalkPlan p) {
     const int64_t w = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
     if (w >= p.n_walkers) return;
     const LabelT* __restrict__ lab = static_cast<const LabelT*>(p.labels);
@@ -34,7 +39,7 @@ __global__ __launch_bounds__(kBlock) void walk_kernel(WalkPlan p) {
 }
 
 template <class Walker, typename LabelT>
-__global__ __launch_bounds__(kBlock) void walk_packed_kernel(const PackedItem* __restrict__ items,
+__global__ __launch_bounds__(kBlock) RMS_WALK_OCCUPANCY void walk_packed_kernel(const PackedItem* __restrict__ items,
                                                              const WalkPlan* __restrict__ plans) {
     const PackedItem it = items[blockIdx.x];
     const WalkPlan p = plans[it.plan];

@@ -209,3 +209,60 @@ def test_errors_reported():
                     params=dict(D=[2.0, 2.0], kappa=[[0, 1e4], [1e4, 0]]))
     assert e.value.code == -4
     sub.close()
+
+
+def _sampled(c, precision, n_sample, label):
+    sub = rms.rms_create_substrate(c["labels"], c["voxel_um"], c["D"], c["kappa"], c["T2"])
+    print(f"[case] {label} full size, precision={precision}", flush=True)
+    g = rms.rms_run(sub, seed=c["seed"], n_walkers=c["n_walkers"], n_steps=c["n_steps"],
+                    dt=c["dt"], waveform=c["waveform"], dirs=c["dirs"], bvals=c["bvals"],
+                    precision=precision, dump=True)
+    sub.close()
+    ids = np.unique(np.linspace(0, c["n_walkers"] - 1, n_sample).astype(np.int64))
+    o = oracle.run(c["labels"], c["voxel_um"], c["D"], c["kappa"], c["T2"], seed=c["seed"],
+                   n_walkers=ids.size, walker_ids=ids, n_steps=c["n_steps"], dt=c["dt"],
+                   waveform=c["waveform"], dirs=c["dirs"], bvals=c["bvals"], n_threads=NT,
+                   dump=True)
+    return g, o, ids
+
+
+def test_cylinder_config_full_size_sampled():
+    """The 32^3 cylinder at its full PGSE timing (delta 2 ms, Delta 10 ms: 60 000
+    steps of 2e-4 ms), 1e4 walkers: sampled walkers match the oracle, b = 0 is
+    exactly 1, and in the z-prism the signal along z follows the free-diffusion
+    product exactly in expectation."""
+    c = configs.cylinder_case()
+    g, o, ids = _sampled(c, rms.RMS_FP64, 48, "cylinder")
+    G, O = g["dump"][ids], o["dump"]
+    assert np.max(np.abs(G[:, 0:3] - O[:, 0:3])) <= 1e-5
+    for col in (4, 5, 6, 7, 11, 12, 13, 14):
+        assert np.array_equal(G[:, col], O[:, col])
+    assert np.all(g["signal"][0, 0] == 1.0)
+    # z: reflections never touch the z motion, so S_z is the free product formula
+    Q = c["dt"] * np.cumsum(c["waveform"][0][::-1])[::-1]
+    bs = c["dt"] * np.sum(Q ** 2)
+    ds = math.sqrt(6 * 2.0 * c["dt"])
+    N = c["n_walkers"]
+    for j, b in enumerate(c["bvals"]):
+        S = np.prod(np.sinc(math.sqrt(b / bs) * Q * ds / np.pi))
+        assert abs(g["signal"][0, j, 2].real - S) < 4 / math.sqrt(N)
+    # free along the prism axis: D_zz = D0 (relative standard error ~ sqrt(2/N))
+    assert abs(g["D"][2] - 2.0) < 4 * 2.0 * math.sqrt(2.0 / N)
+    assert g["D"][0] < 2.0 and g["D"][1] < 2.0  # hindered or restricted across it
+
+
+@pytest.mark.parametrize("precision", [rms.RMS_FP64, rms.RMS_MIXED])
+def test_axon_bundle_full_size_sampled(precision):
+    """The 400 x 400 x 1000 beaded-axon bundle at full size (1e7 walkers x 2e4
+    steps, PGSE and OGSE, 30 directions x 6 b): sampled walkers match the
+    oracle one by one (the mixed form: at least 15 of 16), and |S| <= 1."""
+    c = configs.axon_case()
+    g, o, ids = _sampled(c, precision, 16, "axons")
+    G, O = g["dump"][ids], o["dump"]
+    same = np.all(G[:, [4, 5, 6, 7, 11, 12, 13, 14]] == O[:, [4, 5, 6, 7, 11, 12, 13, 14]], axis=1)
+    same &= np.max(np.abs(G[:, 0:3] - O[:, 0:3]), axis=1) <= 1e-5
+    print(f"identical sampled walkers {same.sum()}/{same.size}", flush=True)
+    assert same.all() if precision == rms.RMS_FP64 else same.sum() >= same.size - 1
+    assert np.all(g["signal"][:, 0] == 1.0)
+    assert np.all(np.abs(g["signal"]) <= 1.0 + 1e-12)
+    assert g["n_permeations"] > 0

@@ -68,7 +68,7 @@ int main() {
                                  : static_cast<uint32_t>(g());
         const double u = (static_cast<double>(w) + 0.5) * 0x1p-32;
         double s, c;
-        rms::dev::sincos_2pi(u, &s, &c);
+        rms::dev::sincos_2pi(u, &s, &c, [](double a, double b, double k) { return std::fma(a, b, k); });
         const long double th = 2.0L * 3.14159265358979323846264338327950288L * u;
         maxe = std::fmax(maxe, std::fabs(static_cast<double>(sinl(th) - s)));
         maxe = std::fmax(maxe, std::fabs(static_cast<double>(cosl(th) - c)));
