@@ -17,10 +17,12 @@
 // Face walk.  Reflection flips one component of the direction and passing
 // changes only the voxel index, so the path length at which a step reaches
 // each axis' face is fixed at the start of the step: e_a = gap_a / |v_a|.  A
-// step sorts the three e_a once and visits them in order while they lie inside
-// the path budget; only a permeation into a label with another step length
-// moves that budget (the remaining share of the step's duration is kept).  The
-// end point on each axis then follows in closed form.
+// step decides which faces lie inside its path budget (gap_a < budget |v_a|)
+// and in which order they come (e_a < e_b iff gap_a |v_b| < gap_b |v_a|) with
+// multiplications only, then visits them in that order; only a permeation
+// into a label with another step length moves the budget (the remaining share
+// of the step's duration is kept), and only then is an e_a divided out.  The
+// end point on each axis follows in closed form.
 //
 // Random numbers: Philox4x32-10 (Salmon et al., SC'11) keyed by the 64-bit
 // seed with counter (index, substream, walker_lo, walker_hi): substream 0
@@ -137,17 +139,6 @@ __host__ __device__ __forceinline__ void sincos_2pi(double u, double* s_out, dou
     *s_out = (q >= 2) ? -sn : sn;
 }
 
-// 1/x for finite normal x > 0: the hardware reciprocal estimate refined by two
-// Newton steps r <- r + r (1 - x r) (within an ulp or two of the correctly
-// rounded quotient).
-__device__ __forceinline__ double recip_pos(double x) {
-    double r = __builtin_amdgcn_rcp(x);
-    double e = fma(-x, r, 1.0);
-    r = fma(r, e, r);
-    e = fma(-x, r, 1.0);
-    return fma(r, e, r);
-}
-
 // sqrt(y) for finite normal y > 0: the hardware reciprocal square root
 // estimate, one coupled Newton step on (sqrt y, 1/(2 sqrt y)) and a final
 // residual correction (Goldschmidt's iteration).
@@ -179,6 +170,35 @@ struct Ids {
 // 2^-ceil(log2 d) <= 1/d.  m and sh come from the host.
 __device__ __forceinline__ uint32_t div_magic(uint32_t n, uint32_t m, uint32_t sh) {
     return static_cast<uint32_t>((static_cast<uint64_t>(n) * m) >> sh);
+}
+
+// Order in which a step reaches the faces of its three axes, by multiplying
+// only: axis a reaches its face after path length e_a = g_a / m_a (g_a >= 0 the
+// gap to the face, m_a = |v_a| > 0), and e_a < e_b exactly when
+// g_a m_b < g_b m_a.  The sign of fma(g_a, m_b, -g_b m_a) decides each of the
+// three pairs; the three bits (e0<e1, e0<e2, e1<e2) index the permutation that
+// sorts (e_0, e_1, e_2), stored as 2-bit fields of two constants.  Patterns no
+// order gives (reachable only by rounding at near-ties) map to (0, 1, 2).
+template <typename Real>
+__host__ __device__ __forceinline__ void event_order(const Real g[3], const Real m[3], int ax[3]) {
+    const auto lt = [&](int i, int j) -> uint32_t {
+        return fma(g[i], m[j], -(g[j] * m[i])) < Real(0) ? 1u : 0u;
+    };
+    const uint32_t sh = 2u * (lt(0, 1) | (lt(0, 2) << 1) | (lt(1, 2) << 2));
+    constexpr uint32_t kFirst = 0x110Au;   // first axis for patterns 0..7: 2 2 0 0 1 0 1 0
+    constexpr uint32_t kSecond = 0x4691u;  // second axis:                  1 0 1 2 2 1 0 1
+    ax[0] = static_cast<int>((kFirst >> sh) & 3u);
+    ax[1] = static_cast<int>((kSecond >> sh) & 3u);
+    ax[2] = 3 - ax[0] - ax[1];
+}
+
+// v[a] for a runtime axis index a in {0, 1, 2}, as two selects (the three
+// reads are unconditional so the compiler does not branch on a)
+template <typename T>
+__device__ __forceinline__ T pick(const T (&v)[3], int a) {
+    const T v0 = v[0], v1 = v[1], v2 = v[2];
+    const T r = a == 1 ? v1 : v2;
+    return a == 0 ? v0 : r;
 }
 
 struct Coords {
@@ -235,30 +255,6 @@ __device__ __forceinline__ Start draw_start(const WalkPlan& p, const Ids& id) {
     return s;
 }
 
-// Order of the three face events of a step: a stable sort of (distance, axis),
-// ties keep x < y < z.
-template <typename Real>
-__device__ __forceinline__ void sort3(const Real e[3], Real s[3], int ax[3]) {
-    s[0] = e[0];
-    s[1] = e[1];
-    s[2] = e[2];
-    ax[0] = 0;
-    ax[1] = 1;
-    ax[2] = 2;
-    auto cswap = [&](int i, int j) {  // compare-exchange as selects, no branches
-        const bool c = s[j] < s[i];
-        const Real lo = c ? s[j] : s[i], hi = c ? s[i] : s[j];
-        const int alo = c ? ax[j] : ax[i], ahi = c ? ax[i] : ax[j];
-        s[i] = lo;
-        s[j] = hi;
-        ax[i] = alo;
-        ax[j] = ahi;
-    };
-    cswap(0, 1);
-    cswap(1, 2);
-    cswap(0, 1);
-}
-
 // ---------------------------------------------------------------------------
 // Double-precision form.
 // ---------------------------------------------------------------------------
@@ -302,36 +298,39 @@ struct WalkerF64 {
         const double rho = 2.0 * sqrt_pos(u1 * (1.0 - u1));
         const double v[3] = {rho * cs, rho * sn, 1.0 - 2.0 * u1};
 
-        // per axis: path length to the face the step moves toward
-        double e[3];
-        uint32_t posm = 0;
+        // per axis: gap to the face the step moves toward and |v|; a face lies
+        // inside the budget sig when gap < sig |v|
+        double g[3], m[3];
+        uint32_t posm = 0, evm = 0;
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
             const bool pos = v[a] > 0.0;
             posm |= pos ? (1u << a) : 0u;
-            const double av = fabs(v[a]);
-            const double gap = fmax(pos ? 1.0 - o[a] : o[a], 0.0);
-            e[a] = av > 0.0 ? gap * recip_pos(av) : INFINITY;
+            m[a] = fabs(v[a]);
+            g[a] = pos ? 1.0 - o[a] : o[a];  // o stays in [0, 1]
+            evm |= g[a] < sig * m[a] ? (1u << a) : 0u;
         }
+        int nev = __builtin_popcount(evm);
+        int ax[3];
+        event_order(g, m, ax);
         int nb[3];
         neighbours(p, lin, posm, nb);
-        double se[3];
-        int ax[3];
-        sort3(e, se, ax);
 
-        double P = 0.0, tau = 1.0, pend = sig;
+        // path length to axis a's face, divided out only after a permeation
+        const auto face_len = [&](int a) {
+            const double va = pick(v, a), oa = pick(o, a);
+            return (va > 0.0 ? 1.0 - oa : oa) / fabs(va);
+        };
+        double P = 0.0, tau = 1.0;
         uint32_t passed = 0, refl = 0;
         int mw_used = 0;
         uint4 mw = make_uint4(0, 0, 0, 0);
-        bool go = true;
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-            const double ek = se[k];
-            const int a = ax[k];
-            go = go && (ek < pend);
-            if (go) {
+            if (k < nev) {
+                const int a = ax[k];
                 ++nface;
-                const int nbk = a == 0 ? nb[0] : (a == 1 ? nb[1] : nb[2]);
+                const int nbk = pick(nb, a);
                 const int nl = lab[nbk];
                 bool cross = true;
                 if (nl != l) {
@@ -342,6 +341,7 @@ struct WalkerF64 {
                     cross = word < p.thr[l * p.n_labels + nl];
                     if (cross) {
                         ++nperm;
+                        const double ek = fmax(face_len(a), P);
                         const double dtau = fmin((ek - P) / sig, tau);
                         R = fma(p.dt * dtau, it2, R);
                         tau -= dtau;
@@ -349,7 +349,12 @@ struct WalkerF64 {
                         l = nl;
                         sig = p.sigma[nl];
                         it2 = p.inv_t2[nl];
-                        pend = fma(tau, sig, P);
+                        // the later faces, in order, that lie inside the new budget
+                        const double pend = fma(tau, sig, P);
+                        nev = k + 1;
+#pragma unroll
+                        for (int j = k + 1; j < 3; ++j)
+                            if (nev == j && face_len(ax[j]) < pend) nev = j + 1;
                     }
                 }
                 if (cross) {
@@ -467,35 +472,37 @@ struct WalkerMixed {
         const float rho = 2.0f * __builtin_sqrtf(u1 * (1.0f - u1));
         const float v[3] = {rho * cs, rho * sn, fmaf(-2.0f, u1, 1.0f)};
 
-        float e[3];
-        uint32_t posm = 0;
+        float g[3], m[3];
+        uint32_t posm = 0, evm = 0;
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
             const bool pos = v[a] > 0.0f;
             posm |= pos ? (1u << a) : 0u;
-            const float av = fabsf(v[a]);
-            const float gap = fmaxf(pos ? 1.0f - o[a] : o[a], 0.0f);
-            e[a] = av > 0.0f ? gap * __builtin_amdgcn_rcpf(av) : INFINITY;
+            m[a] = fabsf(v[a]);
+            g[a] = pos ? 1.0f - o[a] : o[a];  // o stays in [0, 1]
+            evm |= g[a] < sig * m[a] ? (1u << a) : 0u;
         }
+        int nev = __builtin_popcount(evm);
+        int ax[3];
+        event_order(g, m, ax);
         int nb[3];
         neighbours(p, lin, posm, nb);
-        float se[3];
-        int ax[3];
-        sort3(e, se, ax);
 
-        float P = 0.0f, tau = 1.0f, pend = sig;
+        // path length to axis a's face, divided out only after a permeation
+        const auto face_len = [&](int a) {
+            const float va = pick(v, a), oa = pick(o, a);
+            return (va > 0.0f ? 1.0f - oa : oa) / fabsf(va);
+        };
+        float P = 0.0f, tau = 1.0f;
         uint32_t passed = 0, refl = 0;
         int mw_used = 0;
         uint4 mw = make_uint4(0, 0, 0, 0);
-        bool go = true;
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-            const float ek = se[k];
-            const int a = ax[k];
-            go = go && (ek < pend);
-            if (go) {
+            if (k < nev) {
+                const int a = ax[k];
                 ++nface;
-                const int nbk = a == 0 ? nb[0] : (a == 1 ? nb[1] : nb[2]);
+                const int nbk = pick(nb, a);
                 const int nl = lab[nbk];
                 bool cross = true;
                 if (nl != l) {
@@ -506,6 +513,7 @@ struct WalkerMixed {
                     cross = word < p.thr[l * p.n_labels + nl];
                     if (cross) {
                         ++nperm;
+                        const float ek = fmaxf(face_len(a), P);
                         const float dtau = fminf((ek - P) / sig, tau);
                         nsum(R, Rc, static_cast<float>(p.dt) * dtau * it2);
                         tau -= dtau;
@@ -513,7 +521,12 @@ struct WalkerMixed {
                         l = nl;
                         sig = p.sigma_f[nl];
                         it2 = p.inv_t2_f[nl];
-                        pend = fmaf(tau, sig, P);
+                        // the later faces, in order, that lie inside the new budget
+                        const float pend = fmaf(tau, sig, P);
+                        nev = k + 1;
+#pragma unroll
+                        for (int j = k + 1; j < 3; ++j)
+                            if (nev == j && face_len(ax[j]) < pend) nev = j + 1;
                     }
                 }
                 if (cross) {

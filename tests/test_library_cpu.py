@@ -96,3 +96,58 @@ def test_device_sincos_2pi_accuracy(tmp_path):
     err = float(subprocess.run([str(exe)], capture_output=True, text=True, check=True,
                                timeout=120).stdout)
     assert err < 4e-16
+
+
+_ORDER_PROBE = r"""
+#include "rms_device.h"
+#include <cmath>
+#include <cstdio>
+#include <random>
+template <typename Real>
+long check(std::mt19937_64& g, long n) {
+    std::uniform_real_distribution<double> U(0.0, 1.0);
+    long bad = 0;
+    for (long i = 0; i < n; ++i) {
+        Real gg[3], m[3];
+        for (int a = 0; a < 3; ++a) {
+            gg[a] = static_cast<Real>(i % 7 == 0 && a == 1 ? 0.0 : U(g));  // some gaps exactly 0
+            m[a] = static_cast<Real>(U(g) + 1e-9);
+        }
+        int ax[3];
+        rms::dev::event_order(gg, m, ax);
+        bool perm = ax[0] != ax[1] && ax[0] != ax[2] && ax[1] != ax[2] &&
+                    ax[0] >= 0 && ax[0] < 3 && ax[1] >= 0 && ax[1] < 3 && ax[2] >= 0 && ax[2] < 3;
+        if (!perm) { ++bad; continue; }
+        long double e[3];
+        for (int a = 0; a < 3; ++a) e[a] = static_cast<long double>(gg[a]) / m[a];
+        if (e[ax[0]] > e[ax[1]] || e[ax[1]] > e[ax[2]]) ++bad;
+    }
+    return bad;
+}
+int main() {
+    std::mt19937_64 g(7);
+    std::printf("%ld %ld\n", check<double>(g, 1000000), check<float>(g, 1000000));
+    return 0;
+}
+"""
+
+
+def test_device_event_order(tmp_path):
+    """The walker's division-free order of a step's face events (pairwise
+    cross-multiplied comparisons indexing a permutation table) against sorting
+    the path lengths gap / |v| in long double, on the host build of the same
+    function, for both precision forms."""
+    import shutil
+    import subprocess
+    if shutil.which("hipcc") is None:
+        pytest.skip("hipcc not available")
+    src = tmp_path / "order.cpp"
+    exe = tmp_path / "order"
+    src.write_text(_ORDER_PROBE)
+    csrc = os.path.join(ROOT, "paper_2012_06478_amd", "csrc")
+    subprocess.check_call(["hipcc", "-O2", "-std=c++17", "-I", os.path.join(ROOT, "include"),
+                           "-I", csrc, "-o", str(exe), str(src)],
+                          stdout=subprocess.DEVNULL, stderr=subprocess.DEVNULL, timeout=300)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True,
+                         timeout=120).stdout.split()
+    assert out == ["0", "0"], out
