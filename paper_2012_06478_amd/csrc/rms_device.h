@@ -373,25 +373,24 @@ struct WalkerF64 {
         const double lend = fma(tau, sig, P);
         R = fma(p.dt * tau, it2, R);
         // End point per axis from the free end point o + lend v: mirrored about
-        // the face after a reflection, shifted by one voxel after a pass.
+        // the face after a reflection; after a pass the same point, one voxel
+        // further along the axis.  The displacement is that point minus o.
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
             const bool pos = (posm >> a) & 1u;
-            const bool rf = (refl >> a) & 1u;
             const double fr = fma(lend, v[a], o[a]);
-            const double mirror = (pos ? 2.0 : 0.0) - fr;
-            const double on = rf ? mirror : ((passed >> a) & 1u ? fr - (pos ? 1.0 : -1.0) : fr);
-            d[a] += rf ? mirror - o[a] : lend * v[a];
-            o[a] = fmin(fmax(on, 0.0), 1.0);
+            const double t = (refl >> a) & 1u ? (pos ? 2.0 : 0.0) - fr : fr;
+            d[a] += t - o[a];
+            const double shift = (passed >> a) & 1u ? (pos ? 1.0 : -1.0) : 0.0;
+            o[a] = fmin(fmax(t - shift, 0.0), 1.0);
         }
+        // phase: a zero gradient sample adds exactly nothing, so no test for it
 #pragma unroll
         for (int q = 0; q < NS; ++q) {
             const double g = p.gdt[static_cast<int64_t>(q) * p.n_steps + i0];
-            if (g != 0.0) {
-                ph[q][0] = fma(g, d[0], ph[q][0]);
-                ph[q][1] = fma(g, d[1], ph[q][1]);
-                ph[q][2] = fma(g, d[2], ph[q][2]);
-            }
+            ph[q][0] = fma(g, d[0], ph[q][0]);
+            ph[q][1] = fma(g, d[1], ph[q][1]);
+            ph[q][2] = fma(g, d[2], ph[q][2]);
         }
     }
 
@@ -546,11 +545,11 @@ struct WalkerMixed {
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
             const bool pos = (posm >> a) & 1u;
-            const bool rf = (refl >> a) & 1u;
             const bool ps = (passed >> a) & 1u;
             const float fr = fmaf(lend, v[a], o[a]);
-            const float on = rf ? (pos ? 2.0f : 0.0f) - fr : (ps ? fr - (pos ? 1.0f : -1.0f) : fr);
-            o[a] = fminf(fmaxf(on, 0.0f), 1.0f);
+            const float t = (refl >> a) & 1u ? (pos ? 2.0f : 0.0f) - fr : fr;
+            const float shift = ps ? (pos ? 1.0f : -1.0f) : 0.0f;
+            o[a] = fminf(fmaxf(t - shift, 0.0f), 1.0f);
             n[a] += ps ? (pos ? 1 : -1) : 0;
         }
 #pragma unroll
