@@ -131,15 +131,18 @@ const char* rms_last_error(void);
 /* Build a device-resident substrate (sections 2.1.1 and 2.2 item 1).
  *   labels      host array of nx*ny*nz labels, x fastest then y then z,
  *               uint8 (label_bytes = 1) or uint16 (label_bytes = 2); copied;
- *   dims        {nx, ny, nz}, each >= 1, product < 2^31; the volume is
- *               periodic in all three axes;
+ *   dims        {nx, ny, nz}, each >= 1, (nx+2)(ny+2)(nz+2) < 2^31; the
+ *               volume is periodic in all three axes;
  *   voxel_um    isotropic voxel size l_p (um), > 0;
  *   n_labels    number of labels, 1..RMS_MAX_LABELS; every voxel < n_labels;
  *   D, kappa, T2  default tissue parameters (see rms_params);
  *   dead        [n_labels] or NULL: nonzero marks a label no walker starts in
  *               or enters (section 2.2, item 1);
  *   out         receives the handle.
- * The substrate lives on the HIP device current at the call. */
+ * The substrate lives on the HIP device current at the call, as the volume
+ * inside a one-voxel periodic halo: (nx+2)(ny+2)(nz+2) entries of 1 byte
+ * (uint8 labels with n_labels <= 32) or 2 bytes (otherwise).  Returns
+ * RMS_E_OOM if host staging or device memory runs out. */
 int rms_create_substrate(const void* labels, int label_bytes, const int64_t dims[3],
                          double voxel_um, int n_labels, const double* D, const double* kappa,
                          const double* T2, const uint8_t* dead, rms_substrate** out);

@@ -291,12 +291,16 @@ int DeviceRun::create(const rms_substrate& sub, const RunSetup& r, bool resumabl
 
     wp = WalkPlan{};
     wp.labels = sub.d_labels;
-    wp.label_bytes = sub.label_bytes;
+    wp.label_bytes = sub.dev_label_bytes;
     wp.nx = static_cast<int>(sub.dims[0]);
     wp.ny = static_cast<int>(sub.dims[1]);
     wp.nz = static_cast<int>(sub.dims[2]);
+    wp.px = wp.nx + 2;
+    wp.pxy = wp.px * (wp.ny + 2);
     div_magic(static_cast<uint32_t>(sub.dims[0]), &wp.div_nx_m, &wp.div_nx_sh);
     div_magic(static_cast<uint32_t>(sub.dims[0] * sub.dims[1]), &wp.div_nxy_m, &wp.div_nxy_sh);
+    div_magic(static_cast<uint32_t>(wp.px), &wp.div_px_m, &wp.div_px_sh);
+    div_magic(static_cast<uint32_t>(wp.pxy), &wp.div_pxy_m, &wp.div_pxy_sh);
     wp.allowed = sub.d_allowed;
     wp.n_allowed = sub.n_allowed;
     wp.n_labels = sub.n_labels;
@@ -379,8 +383,9 @@ int rms_create_substrate(const void* labels, int label_bytes, const int64_t dims
     if (dims[0] < 1 || dims[1] < 1 || dims[2] < 1)
         return fail(RMS_E_INVALID_ARG, "dims must be >= 1");
     if (dims[0] > (1 << 30) || dims[1] > (1 << 30) || dims[2] > (1 << 30) ||
-        dims[0] * dims[1] * dims[2] >= (int64_t(1) << 31))
-        return fail(RMS_E_INVALID_ARG, "volume must hold fewer than 2^31 voxels");
+        (dims[0] + 2) * (dims[1] + 2) * (dims[2] + 2) >= (int64_t(1) << 31))
+        return fail(RMS_E_INVALID_ARG,
+                    "volume with its one-voxel halo must hold fewer than 2^31 voxels");
     const int64_t nvox = dims[0] * dims[1] * dims[2];
     if (!(voxel_um > 0.0) || !std::isfinite(voxel_um))
         return fail(RMS_E_INVALID_ARG, "voxel_um must be > 0");
@@ -422,11 +427,45 @@ int rms_create_substrate(const void* labels, int label_bytes, const int64_t dims
     }
     sub->n_allowed = any_dead ? static_cast<uint32_t>(allowed.size()) : static_cast<uint32_t>(nvox);
 
+    // padded device volume with the periodic halo and its flags
+    sub->dev_label_bytes = label_bytes == 1 && n_labels <= rms::kMaxLabelsU8 ? 1 : 2;
+    const int64_t nx = dims[0], ny = dims[1], nz = dims[2];
+    const int64_t px = nx + 2, py = ny + 2, pz = nz + 2;
+    const int shift = rms::halo_shift(sub->dev_label_bytes);
+    std::vector<uint16_t> pad16;
+    std::vector<uint8_t> pad8;
+    try {
+        if (sub->dev_label_bytes == 1) pad8.resize(static_cast<size_t>(px * py * pz));
+        else pad16.resize(static_cast<size_t>(px * py * pz));
+    } catch (const std::bad_alloc&) {
+        delete sub;
+        return fail(RMS_E_OOM, "host allocation failed");
+    }
+    for (int64_t zp = 0; zp < pz; ++zp) {
+        const int64_t z = (zp + nz - 1) % nz;
+        const uint32_t fz = zp == 0 || zp == pz - 1 ? 4u : 0u;
+        for (int64_t yp = 0; yp < py; ++yp) {
+            const int64_t y = (yp + ny - 1) % ny;
+            const uint32_t fy = yp == 0 || yp == py - 1 ? 2u : 0u;
+            const int64_t row = (z * ny + y) * nx, prow = (zp * py + yp) * px;
+            for (int64_t xp = 0; xp < px; ++xp) {
+                const int64_t x = (xp + nx - 1) % nx;
+                const uint32_t f = fz | fy | (xp == 0 || xp == px - 1 ? 1u : 0u);
+                const uint32_t l = label_bytes == 1 ? static_cast<const uint8_t*>(labels)[row + x]
+                                                    : static_cast<const uint16_t*>(labels)[row + x];
+                const uint32_t v = l | (f << shift);
+                if (sub->dev_label_bytes == 1) pad8[prow + xp] = static_cast<uint8_t>(v);
+                else pad16[prow + xp] = static_cast<uint16_t>(v);
+            }
+        }
+    }
+    const size_t pad_bytes = static_cast<size_t>(px * py * pz) * sub->dev_label_bytes;
+    const void* pad_src = sub->dev_label_bytes == 1 ? static_cast<const void*>(pad8.data())
+                                                    : static_cast<const void*>(pad16.data());
+
     hipError_t e = hipGetDevice(&sub->device);
-    if (e == hipSuccess) e = hipMalloc(&sub->d_labels, static_cast<size_t>(nvox) * label_bytes);
-    if (e == hipSuccess)
-        e = hipMemcpy(sub->d_labels, labels, static_cast<size_t>(nvox) * label_bytes,
-                      hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMalloc(&sub->d_labels, pad_bytes);
+    if (e == hipSuccess) e = hipMemcpy(sub->d_labels, pad_src, pad_bytes, hipMemcpyHostToDevice);
     if (e == hipSuccess && any_dead) {
         e = hipMalloc(reinterpret_cast<void**>(&sub->d_allowed), allowed.size() * sizeof(uint32_t));
         if (e == hipSuccess)

@@ -81,12 +81,6 @@ __device__ __forceinline__ double unit_open(uint32_t w) {
     return fma(static_cast<double>(w), 0x1p-32, 0x1p-33);
 }
 
-__device__ __forceinline__ int wrap_step(int c, int d, int n) {
-    c += d;
-    c = c < 0 ? c + n : c;
-    return c >= n ? c - n : c;
-}
-
 // fma(a, b, k) with the constant k taken from a scalar register pair: written
 // as the three-operand instruction so the compiler does not keep the
 // polynomial coefficients in vector registers and copy one before every
@@ -205,33 +199,60 @@ struct Coords {
     int c[3];
 };
 
-__device__ __forceinline__ Coords coords_of(const WalkPlan& p, int lin) {
-    const uint32_t nxy = static_cast<uint32_t>(p.nx) * static_cast<uint32_t>(p.ny);
-    const uint32_t z = div_magic(static_cast<uint32_t>(lin), p.div_nxy_m, p.div_nxy_sh);
-    const uint32_t r = static_cast<uint32_t>(lin) - z * nxy;
-    const uint32_t y = div_magic(r, p.div_nx_m, p.div_nx_sh);
+// Coordinates of linear index lin (< 2^31) in a volume of row length n1 and
+// plane size n12, with the division magic numbers of n1 and n12.
+__device__ __forceinline__ Coords coords_of(uint32_t lin, uint32_t n1, uint32_t n12,
+                                            uint32_t m1, uint32_t sh1, uint32_t m12,
+                                            uint32_t sh12) {
+    const uint32_t z = div_magic(lin, m12, sh12);
+    const uint32_t r = lin - z * n12;
+    const uint32_t y = div_magic(r, m1, sh1);
     Coords k;
-    k.c[0] = static_cast<int>(r - y * static_cast<uint32_t>(p.nx));
+    k.c[0] = static_cast<int>(r - y * n1);
     k.c[1] = static_cast<int>(y);
     k.c[2] = static_cast<int>(z);
     return k;
 }
 
-// Linear index of the voxel across the face each axis moves toward (bit a of
-// posm set: toward +a), with periodic wrap.  Every result lies in
-// [0, nx ny nz) because it steps one voxel along an axis from a valid voxel,
-// or jumps to the opposite end of that axis at its edge.
-__device__ __forceinline__ void neighbours(const WalkPlan& p, int lin, uint32_t posm, int nb[3]) {
-    const Coords k = coords_of(p, lin);
-    const int n[3] = {p.nx, p.ny, p.nz};
-    const int st[3] = {1, p.nx, p.nx * p.ny};
+// Index in the padded device volume of voxel `lin` of the nx*ny*nz volume.
+__device__ __forceinline__ int padded_index(const WalkPlan& p, int lin) {
+    const Coords k = coords_of(static_cast<uint32_t>(lin), static_cast<uint32_t>(p.nx),
+                               static_cast<uint32_t>(p.nx) * static_cast<uint32_t>(p.ny),
+                               p.div_nx_m, p.div_nx_sh, p.div_nxy_m, p.div_nxy_sh);
+    return (k.c[0] + 1) + p.px * (k.c[1] + 1) + p.pxy * (k.c[2] + 1);
+}
+
+// Voxel coordinates of an interior index of the padded volume.
+__device__ __forceinline__ Coords volume_coords(const WalkPlan& p, int plin) {
+    Coords k = coords_of(static_cast<uint32_t>(plin), static_cast<uint32_t>(p.px),
+                         static_cast<uint32_t>(p.pxy), p.div_px_m, p.div_px_sh, p.div_pxy_m,
+                         p.div_pxy_sh);
+    k.c[0] -= 1;
+    k.c[1] -= 1;
+    k.c[2] -= 1;
+    return k;
+}
+
+// Halo flag field and label of a padded-volume entry.
+template <typename LabelT>
+struct LabelBits {
+    static constexpr int kShift = halo_shift(static_cast<int>(sizeof(LabelT)));
+    static constexpr uint32_t kMask = (1u << kShift) - 1u;
+};
+
+// A step starts in an interior voxel and crosses at most one face per axis, so
+// every voxel it visits lies within one voxel of the volume along each axis:
+// inside the padded volume.  If it ends in the halo (flag bit a set on the
+// entry it ended in: it passed the face at the volume's end along axis a),
+// it moves back by one period along each flagged axis, in the direction
+// opposite to its pass.
+__device__ __forceinline__ int wrap_halo(const WalkPlan& p, int plin, uint32_t flags,
+                                         uint32_t posm) {
+    const int per[3] = {p.nx, p.ny * p.px, p.nz * p.pxy};
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        const bool pos = (posm >> a) & 1u;
-        const int edge = pos ? n[a] - 1 : 0;  // the coordinate at which the step wraps
-        const int mag = k.c[a] == edge ? st[a] - n[a] * st[a] : st[a];
-        nb[a] = lin + (pos ? mag : -mag);
-    }
+    for (int a = 0; a < 3; ++a)
+        if ((flags >> a) & 1u) plin -= ((posm >> a) & 1u) ? per[a] : -per[a];
+    return plin;
 }
 
 // Start (section 2.2, item 1): uniform over the voxels that are not dead, then
@@ -272,11 +293,11 @@ struct WalkerF64 {
     __device__ __forceinline__ void init(const WalkPlan& p, const LabelT* __restrict__ lab,
                                          const Ids& id) {
         const Start s = draw_start(p, id);
-        lin = s.lin;
+        lin = padded_index(p, s.lin);
         o[0] = unit_open(s.wox);
         o[1] = unit_open(s.woy);
         o[2] = unit_open(s.woz);
-        l = l0 = lab[s.lin];
+        l = l0 = lab[lin];  // interior: no flags
         sig = p.sigma[l];
         it2 = p.inv_t2[l];
         d[0] = d[1] = d[2] = 0.0;
@@ -302,9 +323,12 @@ struct WalkerF64 {
         // inside the budget sig when gap < sig |v|
         double g[3], m[3];
         uint32_t posm = 0, evm = 0;
+        int sst[3];  // padded-volume index step across the face each axis moves toward
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
             const bool pos = v[a] > 0.0;
+            const int st = a == 0 ? 1 : (a == 1 ? p.px : p.pxy);
+            sst[a] = pos ? st : -st;
             posm |= pos ? (1u << a) : 0u;
             m[a] = fabs(v[a]);
             g[a] = pos ? 1.0 - o[a] : o[a];  // o stays in [0, 1]
@@ -313,8 +337,20 @@ struct WalkerF64 {
         int nev = __builtin_popcount(evm);
         int ax[3];
         event_order(g, m, ax);
-        int nb[3];
-        neighbours(p, lin, posm, nb);
+        // Entries of the voxels the events reach if every face passes (the
+        // common case), loaded together so the step waits for memory once
+        // rather than once per event.
+        const int nev0 = nev;
+        uint32_t rsp[3] = {0u, 0u, 0u};
+        {
+            int c = lin;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                c += pick(sst, ax[k]);
+                if (k < nev0) rsp[k] = lab[c];
+            }
+        }
+        bool spec = true;  // no reflection yet: rsp holds the entries of the voxels reached
 
         // path length to axis a's face, divided out only after a permeation
         const auto face_len = [&](int a) {
@@ -323,6 +359,7 @@ struct WalkerF64 {
         };
         double P = 0.0, tau = 1.0;
         uint32_t passed = 0, refl = 0;
+        uint32_t rawc = 0;  // entry of the voxel last passed into (its halo flags)
         int mw_used = 0;
         uint4 mw = make_uint4(0, 0, 0, 0);
 #pragma unroll
@@ -330,8 +367,10 @@ struct WalkerF64 {
             if (k < nev) {
                 const int a = ax[k];
                 ++nface;
-                const int nbk = pick(nb, a);
-                const int nl = lab[nbk];
+                const int nbk = lin + pick(sst, a);
+                uint32_t raw = rsp[k];
+                if (!(spec && k < nev0)) raw = lab[nbk];
+                const int nl = static_cast<int>(raw & LabelBits<LabelT>::kMask);
                 bool cross = true;
                 if (nl != l) {
                     ++nhit;
@@ -358,18 +397,17 @@ struct WalkerF64 {
                     }
                 }
                 if (cross) {
-                    // into the neighbour: the other axes' neighbours shift with it
                     passed |= 1u << a;
-                    const int dl = nbk - lin;
                     lin = nbk;
-                    nb[0] += dl;
-                    nb[1] += dl;
-                    nb[2] += dl;
+                    rawc = raw;
                 } else {
                     refl |= 1u << a;
+                    spec = false;
                 }
             }
         }
+        const uint32_t halo = rawc >> LabelBits<LabelT>::kShift;
+        if (__builtin_expect(halo != 0u, 0)) lin = wrap_halo(p, lin, halo, posm);
         const double lend = fma(tau, sig, P);
         R = fma(p.dt * tau, it2, R);
         // End point per axis from the free end point o + lend v: mirrored about
@@ -396,7 +434,7 @@ struct WalkerF64 {
 
     // Per-walker record (layout of RMS_DUMP_WIDTH in rms.h).
     __device__ __forceinline__ void finish(const WalkPlan& p, double* out) const {
-        const Coords k = coords_of(p, lin);
+        const Coords k = volume_coords(p, lin);
         out[0] = d[0] * p.voxel_um;
         out[1] = d[1] * p.voxel_um;
         out[2] = d[2] * p.voxel_um;
@@ -444,12 +482,12 @@ struct WalkerMixed {
     __device__ __forceinline__ void init(const WalkPlan& p, const LabelT* __restrict__ lab,
                                          const Ids& id) {
         const Start s = draw_start(p, id);
-        lin = s.lin;
+        lin = padded_index(p, s.lin);
         o[0] = o0[0] = unit_open_f(s.wox);
         o[1] = o0[1] = unit_open_f(s.woy);
         o[2] = o0[2] = unit_open_f(s.woz);
         n[0] = n[1] = n[2] = 0;
-        l = l0 = lab[s.lin];
+        l = l0 = lab[lin];  // interior: no flags
         sig = p.sigma_f[l];
         it2 = p.inv_t2_f[l];
         R = Rc = 0.0f;
@@ -473,9 +511,12 @@ struct WalkerMixed {
 
         float g[3], m[3];
         uint32_t posm = 0, evm = 0;
+        int sst[3];  // padded-volume index step across the face each axis moves toward
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
             const bool pos = v[a] > 0.0f;
+            const int st = a == 0 ? 1 : (a == 1 ? p.px : p.pxy);
+            sst[a] = pos ? st : -st;
             posm |= pos ? (1u << a) : 0u;
             m[a] = fabsf(v[a]);
             g[a] = pos ? 1.0f - o[a] : o[a];  // o stays in [0, 1]
@@ -484,8 +525,20 @@ struct WalkerMixed {
         int nev = __builtin_popcount(evm);
         int ax[3];
         event_order(g, m, ax);
-        int nb[3];
-        neighbours(p, lin, posm, nb);
+        // Entries of the voxels the events reach if every face passes (the
+        // common case), loaded together so the step waits for memory once
+        // rather than once per event.
+        const int nev0 = nev;
+        uint32_t rsp[3] = {0u, 0u, 0u};
+        {
+            int c = lin;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                c += pick(sst, ax[k]);
+                if (k < nev0) rsp[k] = lab[c];
+            }
+        }
+        bool spec = true;  // no reflection yet: rsp holds the entries of the voxels reached
 
         // path length to axis a's face, divided out only after a permeation
         const auto face_len = [&](int a) {
@@ -494,6 +547,7 @@ struct WalkerMixed {
         };
         float P = 0.0f, tau = 1.0f;
         uint32_t passed = 0, refl = 0;
+        uint32_t rawc = 0;  // entry of the voxel last passed into (its halo flags)
         int mw_used = 0;
         uint4 mw = make_uint4(0, 0, 0, 0);
 #pragma unroll
@@ -501,8 +555,10 @@ struct WalkerMixed {
             if (k < nev) {
                 const int a = ax[k];
                 ++nface;
-                const int nbk = pick(nb, a);
-                const int nl = lab[nbk];
+                const int nbk = lin + pick(sst, a);
+                uint32_t raw = rsp[k];
+                if (!(spec && k < nev0)) raw = lab[nbk];
+                const int nl = static_cast<int>(raw & LabelBits<LabelT>::kMask);
                 bool cross = true;
                 if (nl != l) {
                     ++nhit;
@@ -530,16 +586,16 @@ struct WalkerMixed {
                 }
                 if (cross) {
                     passed |= 1u << a;
-                    const int dl = nbk - lin;
                     lin = nbk;
-                    nb[0] += dl;
-                    nb[1] += dl;
-                    nb[2] += dl;
+                    rawc = raw;
                 } else {
                     refl |= 1u << a;
+                    spec = false;
                 }
             }
         }
+        const uint32_t halo = rawc >> LabelBits<LabelT>::kShift;
+        if (__builtin_expect(halo != 0u, 0)) lin = wrap_halo(p, lin, halo, posm);
         const float lend = fmaf(tau, sig, P);
         nsum(R, Rc, static_cast<float>(p.dt) * tau * it2);
 #pragma unroll
@@ -564,7 +620,7 @@ struct WalkerMixed {
     }
 
     __device__ __forceinline__ void finish(const WalkPlan& p, double* out) const {
-        const Coords k = coords_of(p, lin);
+        const Coords k = volume_coords(p, lin);
 #pragma unroll
         for (int a = 0; a < 3; ++a)
             out[a] = (static_cast<double>(n[a]) +

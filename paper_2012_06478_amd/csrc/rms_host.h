@@ -14,13 +14,14 @@
 
 struct rms_substrate {
     int device = 0;
-    int label_bytes = 1;
+    int label_bytes = 1;      // bytes per label of the caller's volume
+    int dev_label_bytes = 1;  // bytes per entry of the padded device volume
     int64_t dims[3] = {0, 0, 0};
     double voxel_um = 0.0;
     int n_labels = 0;
     std::vector<double> D, kappa, T2;
     std::vector<uint8_t> dead;
-    void* d_labels = nullptr;
+    void* d_labels = nullptr;  // padded volume with halo flags (rms_internal.h)
     uint32_t* d_allowed = nullptr;
     uint32_t n_allowed = 0;
 };

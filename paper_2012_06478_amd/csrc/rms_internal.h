@@ -11,13 +11,25 @@ namespace rms {
 constexpr int kBlock = 256;  // threads per block of every kernel here
 constexpr int kDumpFixed = 15;
 
+// Device label volume: the nx*ny*nz labels inside a one-voxel periodic halo,
+// (nx+2)*(ny+2)*(nz+2) entries, x fastest, so the voxel across any face of an
+// interior voxel is one stride away.  A halo entry holds the label of the
+// periodic image, with bit a of its flag field set when it lies beyond the
+// volume along axis a; interior entries have no flags.  uint8 entries (at most
+// kMaxLabelsU8 labels) keep the flags in bits 5-7, uint16 entries in 13-15.
+constexpr int kMaxLabelsU8 = 32;
+constexpr int halo_shift(int label_bytes) { return label_bytes == 1 ? 5 : 13; }
+
 // Everything the walk kernel reads.  All pointers are device pointers.
 struct WalkPlan {
-    const void* labels;  // nx*ny*nz labels, x fastest (uint8 or uint16)
-    int label_bytes;
+    const void* labels;  // padded device label volume (above), uint8 or uint16
+    int label_bytes;     // bytes per entry of `labels`
     int nx, ny, nz;
+    int px, pxy;         // strides of y and z in the padded volume: nx+2, (nx+2)(ny+2)
     uint32_t div_nx_m, div_nx_sh;    // n / nx == (n div_nx_m) >> div_nx_sh for n < 2^31
     uint32_t div_nxy_m, div_nxy_sh;  // n / (nx ny), likewise
+    uint32_t div_px_m, div_px_sh;    // n / px, likewise
+    uint32_t div_pxy_m, div_pxy_sh;  // n / pxy, likewise
     const uint32_t* allowed;  // ascending linear indices of non-dead voxels, or null (all)
     uint32_t n_allowed;
     int n_labels;

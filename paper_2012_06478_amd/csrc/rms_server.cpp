@@ -157,7 +157,7 @@ void rms_server::loop() {
         // one packed launch per (precision, label width, shape count)
         std::map<std::tuple<int, int, int>, std::vector<Request*>> groups;
         for (Request* r : active)
-            groups[{r->setup.precision, r->setup.sub->label_bytes, r->setup.n_shapes}].push_back(r);
+            groups[{r->setup.precision, r->setup.sub->dev_label_bytes, r->setup.n_shapes}].push_back(r);
         std::vector<rms::WalkPlan> plans;
         std::vector<rms::PackedItem> items;
         std::vector<std::tuple<int, int, int, size_t, size_t>> launches_todo;  // key, item range

@@ -115,6 +115,45 @@ def test_dead_space_and_odd_steps():
     _assert_summary(g, o, 1e-9)
 
 
+def test_uint8_labels_beyond_flag_room():
+    """uint8 volume with 46 labels: more than the uint8 device entries leave
+    room for next to the halo flags, so the device volume is widened to
+    uint16; permeable membranes, unequal D."""
+    lab16, _ = ellipsoid_packing(n=40, n_cells=45, semi_um=(0.4, 0.9), seed=21)
+    lab = lab16.astype(np.uint8)
+    L = int(lab.max()) + 1
+    assert L > 33
+    D = np.full(L, 1.7)
+    D[0] = 2.4
+    kap = np.zeros((L, L))
+    kap[0, 1:] = kap[1:, 0] = 0.3
+    n, dt = 1500, 2e-4
+    g, o = _both(lab, 0.1, D, kap, None, seed=5, n_walkers=1500, n_steps=n, dt=dt,
+                 waveform=pgse(n, dt, 0.05, 0.2), dirs=six_dirs(), bvals=[0.0, 1.0])
+    assert o["n_permeations"] > 50
+    _assert_walkers(g, o, 1e-9)
+    _assert_summary(g, o, 1e-9)
+
+
+@pytest.mark.parametrize("dtype", [np.uint8, np.uint16])
+def test_thin_axes_periodic_wrap(dtype):
+    """1 x 2 x 37 voxels of random labels with permeable membranes: about a
+    third of the steps cross the volume's end along x or y, so the periodic
+    wrap through the device halo is taken constantly (one-voxel axis: the
+    voxel is its own neighbour)."""
+    rng = np.random.default_rng(11)
+    lab = rng.integers(0, 3, size=(37, 2, 1)).astype(dtype)
+    D = np.array([2.0, 1.2, 2.6])
+    kap = np.full((3, 3), 0.5)
+    np.fill_diagonal(kap, 0.0)
+    n, dt = 900, 2e-4
+    g, o = _both(lab, 0.1, D, kap, None, seed=8, n_walkers=700, n_steps=n, dt=dt,
+                 waveform=pgse(n, dt, 0.03, 0.1), dirs=six_dirs(), bvals=[0.0, 2.0])
+    assert o["n_face_events"] > 0.5 * 700 * n and o["n_permeations"] > 500
+    _assert_walkers(g, o, 1e-9)
+    _assert_summary(g, o, 1e-9)
+
+
 @pytest.mark.parametrize("n_walkers,n_steps", [(1, 0), (1, 1), (65, 2), (257, 3)])
 def test_degenerate_sizes(n_walkers, n_steps):
     lab = cylinder_z(8, 3.0)
