@@ -244,6 +244,8 @@ size_t device_bytes(const RunSetup& r, bool resumable) {
     if (resumable)
         b += static_cast<size_t>(r.n_walkers) *
              walker_state_bytes(r.precision, r.sub->label_bytes, r.n_shapes);
+    else
+        b += order_bytes(r.n_walkers);
     return b + 64 * 1024;  // allocation granularity slack
 }
 
@@ -277,6 +279,9 @@ int DeviceRun::create(const rms_substrate& sub, const RunSetup& r, bool resumabl
                           walker_state_bytes(r.precision, sub.label_bytes, r.n_shapes));
         d_state = st;
     }
+    uint32_t* d_order = nullptr;
+    if (!resumable && order_bytes(r.n_walkers) > 0)
+        RMS_ALLOC(d_order, order_bytes(r.n_walkers) / sizeof(uint32_t));
 #undef RMS_ALLOC
     RMS_HIP(upload(d_sigma, r.sigma, s));
     RMS_HIP(upload(d_it2, r.inv_t2, s));
@@ -319,6 +324,8 @@ int DeviceRun::create(const rms_substrate& sub, const RunSetup& r, bool resumabl
     wp.gdt_f = d_gdt_f;
     wp.wstate = d_wstate;
     wp.state = d_state;
+    wp.order = d_order;
+    wp.n_slots = d_order ? order_slots(r.n_walkers) : r.n_walkers;
 
     rp = ReducePlan{};
     rp.wstate = d_wstate;
@@ -528,6 +535,7 @@ int rms_run(const rms_substrate* sub, const rms_params* params, uint64_t seed, i
     } eguard{&ev0, &ev1};
     RMS_HIP(hipEventCreate(&ev0));
     RMS_HIP(hipEventCreate(&ev1));
+    RMS_HIP(rms::launch_order(dr.wp, stream));
     RMS_HIP(hipEventRecord(ev0, stream));
     RMS_HIP(rms::launch_walk(dr.wp, precision, stream));
     RMS_HIP(hipEventRecord(ev1, stream));

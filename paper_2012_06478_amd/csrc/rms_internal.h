@@ -48,7 +48,12 @@ struct WalkPlan {
     const float* gdt_f;  // fp32 copy for the mixed form
     double* wstate;      // [n_walkers][kDumpFixed + 3 n_shapes] per-walker results
     void* state;         // [n_walkers] resumable walker states (packed launches), or null
+    uint32_t* order;     // [n_slots] walker of each thread slot (kNoWalker: none), or
+                         // null: slot i runs walker i; followed by the ordering scratch
+    int64_t n_slots;
 };
+
+constexpr uint32_t kNoWalker = 0xFFFFFFFFu;
 
 // One block of a packed launch: walkers [first_walker, first_walker + kBlock)
 // of plan `plan`, steps [step_begin, step_end).
@@ -88,6 +93,13 @@ hipError_t launch_walk(const WalkPlan& p, int precision, hipStream_t s);
 // state again (or the final record when step_end == n_steps).
 hipError_t launch_walk_packed(const PackedItem* items, int n_items, const WalkPlan* plans,
                               int precision, int label_bytes, int n_shapes, hipStream_t s);
+// Walker order for one run (rms_walk.hip): slots in blocks that run on one
+// XCD take walkers whose start voxels are close.  order_bytes() is the device
+// memory it needs (0 when the run keeps slot i = walker i), order_slots() the
+// thread slots of the walk launch; launch_order() fills p.order.
+size_t order_bytes(int64_t n_walkers);
+int64_t order_slots(int64_t n_walkers);
+hipError_t launch_order(const WalkPlan& p, hipStream_t s);
 // Bytes of one resumable walker state.
 size_t walker_state_bytes(int precision, int label_bytes, int n_shapes);
 hipError_t launch_reduce(const ReducePlan& p, hipStream_t s);

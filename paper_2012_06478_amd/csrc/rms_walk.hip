@@ -27,8 +27,16 @@ using dev::Ids;
 
 template <class Walker, typename LabelT>
 __global__ __launch_bounds__(kBlock) RMS_WALK_OCCUPANCY void walk_kernel(WalkPlan p) {
-    const int64_t w = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
-    if (w >= p.n_walkers) return;
+    const int64_t slot = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+    int64_t w = slot;
+    if (p.order) {
+        if (slot >= p.n_slots) return;
+        const uint32_t o = p.order[slot];
+        if (o == kNoWalker) return;
+        w = o;
+    } else if (w >= p.n_walkers) {
+        return;
+    }
     const LabelT* __restrict__ lab = static_cast<const LabelT*>(p.labels);
     const Ids id{static_cast<uint32_t>(w), static_cast<uint32_t>(w >> 32),
                  static_cast<uint32_t>(p.seed), static_cast<uint32_t>(p.seed >> 32)};
@@ -59,9 +67,102 @@ __global__ __launch_bounds__(kBlock) RMS_WALK_OCCUPANCY void walk_packed_kernel(
         *st = W;
 }
 
+// ---------------------------------------------------------------------------
+// Walker order.  The walk gathers labels at random places of the volume; a
+// 16 MB volume misses the 4 MB L2 of each XCD.  Blocks are dealt to the eight
+// XCDs round-robin (block b on XCD b mod 8), so the walkers are sorted by the
+// Morton code of their start cell (64 cells per axis), the sorted list is cut
+// into eight equal runs, and run c fills blocks c, c + 8, c + 16, ...: each
+// XCD then walks one compact part of the volume and the lanes of a wave start
+// close together.  A walker's result depends only on its index, so the order
+// changes no result.  Counting sort: cell histogram, one-block scan, scatter
+// with atomic slot counters (the order of walkers inside one cell is
+// arbitrary).
+
+constexpr int kXcds = 8;
+constexpr int kCellBits = 6;
+constexpr uint32_t kCells = 1u << (3 * kCellBits);
+constexpr int kScanThreads = 1024;
+
+int64_t order_chunk(int64_t n) {  // walkers per XCD run, whole blocks
+    const int64_t per = (n + kXcds - 1) / kXcds;
+    return (per + kBlock - 1) / kBlock * kBlock;
+}
+
+bool order_used(int64_t n) { return n >= 1 && n < static_cast<int64_t>(kNoWalker); }
+
+__device__ __forceinline__ uint32_t spread3(uint32_t v) {  // bit i -> bit 3i
+    uint32_t r = 0;
+#pragma unroll
+    for (int i = 0; i < kCellBits; ++i) r |= ((v >> i) & 1u) << (3 * i);
+    return r;
+}
+
+__global__ __launch_bounds__(kBlock) void order_init_kernel(uint32_t* order, int64_t n_slots,
+                                                            uint32_t* count) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+    if (i < n_slots) order[i] = kNoWalker;
+    if (i < kCells) count[i] = 0u;
+}
+
+__global__ __launch_bounds__(kBlock) void order_keys_kernel(WalkPlan p, uint32_t* count,
+                                                            uint32_t* keys) {
+    const int64_t w = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+    if (w >= p.n_walkers) return;
+    const Ids id{static_cast<uint32_t>(w), static_cast<uint32_t>(w >> 32),
+                 static_cast<uint32_t>(p.seed), static_cast<uint32_t>(p.seed >> 32)};
+    const dev::Start st = dev::draw_start(p, id);
+    const dev::Coords k = dev::coords_of(static_cast<uint32_t>(st.lin), static_cast<uint32_t>(p.nx),
+                                         static_cast<uint32_t>(p.nx) * static_cast<uint32_t>(p.ny),
+                                         p.div_nx_m, p.div_nx_sh, p.div_nxy_m, p.div_nxy_sh);
+    const int n[3] = {p.nx, p.ny, p.nz};
+    uint32_t key = 0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const uint32_t c = static_cast<uint32_t>((static_cast<uint64_t>(k.c[a]) << kCellBits) / n[a]);
+        key |= spread3(c) << a;
+    }
+    keys[w] = key;
+    atomicAdd(&count[key], 1u);
+}
+
+// Exclusive prefix sum of the kCells cell counts, in place, by one block.
+__global__ __launch_bounds__(kScanThreads) void order_scan_kernel(uint32_t* count) {
+    constexpr int per = kCells / kScanThreads;
+    __shared__ uint32_t part[kScanThreads];
+    uint32_t* c = count + threadIdx.x * per;
+    uint32_t sum = 0;
+    for (int i = 0; i < per; ++i) sum += c[i];
+    part[threadIdx.x] = sum;
+    __syncthreads();
+    for (int off = 1; off < kScanThreads; off <<= 1) {  // inclusive Hillis-Steele scan
+        const uint32_t v = threadIdx.x >= static_cast<unsigned>(off) ? part[threadIdx.x - off] : 0u;
+        __syncthreads();
+        part[threadIdx.x] += v;
+        __syncthreads();
+    }
+    uint32_t run = part[threadIdx.x] - sum;
+    for (int i = 0; i < per; ++i) {
+        const uint32_t v = c[i];
+        c[i] = run;
+        run += v;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void order_scatter_kernel(const uint32_t* keys, uint32_t* next,
+                                                               uint32_t* order, int64_t n,
+                                                               int64_t chunk) {
+    const int64_t w = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+    if (w >= n) return;
+    const int64_t pos = atomicAdd(&next[keys[w]], 1u);  // place in the sorted list
+    const int64_t c = pos / chunk, j = pos - c * chunk;
+    order[((j / kBlock) * kXcds + c) * kBlock + j % kBlock] = static_cast<uint32_t>(w);
+}
+
 template <template <typename, int> class Walker, typename LabelT>
 hipError_t run_ns(const WalkPlan& p, hipStream_t s) {
-    const dim3 grid(static_cast<unsigned>((p.n_walkers + kBlock - 1) / kBlock));
+    const int64_t slots = p.order ? p.n_slots : p.n_walkers;
+    const dim3 grid(static_cast<unsigned>((slots + kBlock - 1) / kBlock));
     switch (p.n_shapes) {
         case 0: walk_kernel<Walker<LabelT, 0>, LabelT><<<grid, kBlock, 0, s>>>(p); break;
         case 1: walk_kernel<Walker<LabelT, 1>, LabelT><<<grid, kBlock, 0, s>>>(p); break;
@@ -101,6 +202,29 @@ size_t state_bytes_ns(int ns) {
 }
 
 }  // namespace
+
+size_t order_bytes(int64_t n) {
+    if (!order_used(n)) return 0;
+    return static_cast<size_t>(kXcds * order_chunk(n) + kCells + n) * sizeof(uint32_t);
+}
+
+int64_t order_slots(int64_t n) { return order_used(n) ? kXcds * order_chunk(n) : n; }
+
+// Scratch behind p.order: order[n_slots], count[kCells], keys[n_walkers].
+hipError_t launch_order(const WalkPlan& p, hipStream_t s) {
+    if (!p.order) return hipSuccess;
+    uint32_t* count = p.order + p.n_slots;
+    uint32_t* keys = count + kCells;
+    const int64_t n = p.n_walkers;
+    const int64_t init = p.n_slots > kCells ? p.n_slots : kCells;
+    order_init_kernel<<<dim3(static_cast<unsigned>((init + kBlock - 1) / kBlock)), kBlock, 0, s>>>(
+        p.order, p.n_slots, count);
+    const dim3 grid(static_cast<unsigned>((n + kBlock - 1) / kBlock));
+    order_keys_kernel<<<grid, kBlock, 0, s>>>(p, count, keys);
+    order_scan_kernel<<<1, kScanThreads, 0, s>>>(count);
+    order_scatter_kernel<<<grid, kBlock, 0, s>>>(keys, count, p.order, n, order_chunk(n));
+    return hipGetLastError();
+}
 
 hipError_t launch_walk(const WalkPlan& p, int precision, hipStream_t s) {
     if (p.n_walkers <= 0) return hipSuccess;
