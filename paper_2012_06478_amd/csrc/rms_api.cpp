@@ -211,7 +211,6 @@ int prepare_run(const rms_substrate* sub, const rms_params* params, uint64_t see
                 bvals[j] > 0.0 ? std::sqrt(bvals[j] / r.b_disc[s]) : 0.0;
         }
     }
-    r.gdt_f.assign(r.gdt.begin(), r.gdt.end());
     r.unit.assign(static_cast<size_t>(n_dirs) * 3, 0.0);
     for (int d = 0; d < n_dirs; ++d) {
         const double* g = dirs + 3 * d;
@@ -236,7 +235,7 @@ int prepare_run(const rms_substrate* sub, const rms_params* params, uint64_t see
 size_t device_bytes(const RunSetup& r, bool resumable) {
     const size_t L = static_cast<size_t>(r.sub->n_labels);
     size_t b = L * (2 * sizeof(double) + 2 * sizeof(float)) + L * L * sizeof(uint32_t);
-    b += r.gdt.size() * (sizeof(double) + sizeof(float));
+    b += r.gdt.size() * sizeof(double);
     b += static_cast<size_t>(r.n_walkers) * r.width * sizeof(double);
     b += r.kg.size() * sizeof(double) + r.sig_shape.size() * sizeof(int);
     b += static_cast<size_t>(r.n_acc) * r.n_blocks * sizeof(double);
@@ -254,7 +253,7 @@ int DeviceRun::create(const rms_substrate& sub, const RunSetup& r, bool resumabl
     s = stream;
     const size_t L = static_cast<size_t>(sub.n_labels);
     double *d_sigma, *d_it2, *d_gdt, *d_wstate, *d_kg, *d_partial, *d_sums, *d_res, *d_dirs;
-    float *d_sigma_f, *d_it2_f, *d_gdt_f;
+    float *d_sigma_f, *d_it2_f;
     uint32_t* d_thr;
     int* d_sig_shape;
     void* d_state = nullptr;
@@ -265,7 +264,6 @@ int DeviceRun::create(const rms_substrate& sub, const RunSetup& r, bool resumabl
     RMS_ALLOC(d_it2_f, L);
     RMS_ALLOC(d_thr, L * L);
     RMS_ALLOC(d_gdt, r.gdt.size());
-    RMS_ALLOC(d_gdt_f, r.gdt_f.size());
     RMS_ALLOC(d_wstate, static_cast<size_t>(r.n_walkers) * r.width);
     RMS_ALLOC(d_kg, r.kg.size());
     RMS_ALLOC(d_sig_shape, r.sig_shape.size());
@@ -289,7 +287,6 @@ int DeviceRun::create(const rms_substrate& sub, const RunSetup& r, bool resumabl
     RMS_HIP(upload(d_it2_f, r.inv_t2_f, s));
     RMS_HIP(upload(d_thr, r.thr, s));
     RMS_HIP(upload(d_gdt, r.gdt, s));
-    RMS_HIP(upload(d_gdt_f, r.gdt_f, s));
     RMS_HIP(upload(d_kg, r.kg, s));
     RMS_HIP(upload(d_sig_shape, r.sig_shape, s));
     RMS_HIP(upload(d_dirs, r.unit, s));
@@ -321,7 +318,6 @@ int DeviceRun::create(const rms_substrate& sub, const RunSetup& r, bool resumabl
     wp.voxel_um = sub.voxel_um;
     wp.n_shapes = r.n_shapes;
     wp.gdt = d_gdt;
-    wp.gdt_f = d_gdt_f;
     wp.wstate = d_wstate;
     wp.state = d_state;
     wp.order = d_order;

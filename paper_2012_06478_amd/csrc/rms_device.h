@@ -39,12 +39,12 @@
 // so a coordinate keeps the same absolute precision anywhere in the volume
 // (the point of taking voxel membership from the integer part, section
 // 2.1.1).  Directions take u1, u2 from the top 24 bits of the same words and
-// use the hardware sine and cosine (argument in
-// revolutions, so 2 pi u needs no range reduction); face distances, end points
-// and budgets are fp32; the displacement is the exact count of voxels crossed
-// plus the fp32 offset change; the phase and R are Neumaier-compensated fp32
-// sums.  Permeation uses the same 32-bit thresholds and words as the fp64
-// form.
+// use the hardware sine and cosine (argument in revolutions, so 2 pi u needs
+// no range reduction); face tests, end points and budgets are fp32; the
+// displacement is the exact count of voxels crossed plus the fp32 offset
+// change; the phase and R accumulate in fp64 (a double FMA issues at the fp32
+// rate on gfx950, so this costs less than a compensated fp32 sum).
+// Permeation uses the same 32-bit thresholds and words as the fp64 form.
 #pragma once
 
 #include "rms_internal.h"
@@ -145,13 +145,6 @@ __device__ __forceinline__ double sqrt_pos(double y) {
     h = fma(h, e, h);
     const double d = fma(-g, g, y);
     return fma(d, h, g);
-}
-
-// Neumaier compensated accumulation: s + c carries the sum of every x added.
-__device__ __forceinline__ void nsum(float& s, float& c, float x) {
-    const float t = s + x;
-    c += fabsf(s) >= fabsf(x) ? (s - t) + x : (x - t) + s;
-    s = t;
 }
 
 // Walker identity and Philox key.
@@ -476,8 +469,8 @@ struct WalkerMixed {
     float o[3];   // offset in the voxel, [0, 1]
     float o0[3];  // offset at the start
     float sig, it2;
-    float R, Rc;  // compensated R
-    float ph[kShapes][3], phc[kShapes][3];
+    double R;             // sum of t_c / T2_c
+    double ph[kShapes][3];  // phase vector, voxel units x ms
 
     __device__ __forceinline__ void init(const WalkPlan& p, const LabelT* __restrict__ lab,
                                          const Ids& id) {
@@ -490,11 +483,11 @@ struct WalkerMixed {
         l = l0 = lab[lin];  // interior: no flags
         sig = p.sigma_f[l];
         it2 = p.inv_t2_f[l];
-        R = Rc = 0.0f;
+        R = 0.0;
 #pragma unroll
         for (int q = 0; q < kShapes; ++q)
 #pragma unroll
-            for (int a = 0; a < 3; ++a) ph[q][a] = phc[q][a] = 0.0f;
+            for (int a = 0; a < 3; ++a) ph[q][a] = 0.0;
         nface = nhit = nperm = 0;
     }
 
@@ -570,7 +563,7 @@ struct WalkerMixed {
                         ++nperm;
                         const float ek = fmaxf(face_len(a), P);
                         const float dtau = fminf((ek - P) / sig, tau);
-                        nsum(R, Rc, static_cast<float>(p.dt) * dtau * it2);
+                        R += static_cast<double>(static_cast<float>(p.dt) * dtau * it2);
                         tau -= dtau;
                         P = ek;
                         l = nl;
@@ -597,7 +590,7 @@ struct WalkerMixed {
         const uint32_t halo = rawc >> LabelBits<LabelT>::kShift;
         if (__builtin_expect(halo != 0u, 0)) lin = wrap_halo(p, lin, halo, posm);
         const float lend = fmaf(tau, sig, P);
-        nsum(R, Rc, static_cast<float>(p.dt) * tau * it2);
+        R += static_cast<double>(static_cast<float>(p.dt) * tau * it2);
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
             const bool pos = (posm >> a) & 1u;
@@ -610,11 +603,13 @@ struct WalkerMixed {
         }
 #pragma unroll
         for (int q = 0; q < NS; ++q) {
-            const float g = p.gdt_f[static_cast<int64_t>(q) * p.n_steps + i0];
-            if (g != 0.0f) {
+            const double g = p.gdt[static_cast<int64_t>(q) * p.n_steps + i0];
+            if (g != 0.0) {
 #pragma unroll
-                for (int a = 0; a < 3; ++a)
-                    nsum(ph[q][a], phc[q][a], g * (static_cast<float>(n[a]) + (o[a] - o0[a])));
+                for (int a = 0; a < 3; ++a)  // displacement n + o - o0, exact in double
+                    ph[q][a] = fma(g, static_cast<double>(n[a]) + (static_cast<double>(o[a]) -
+                                                                   static_cast<double>(o0[a])),
+                                   ph[q][a]);
             }
         }
     }
@@ -625,7 +620,7 @@ struct WalkerMixed {
         for (int a = 0; a < 3; ++a)
             out[a] = (static_cast<double>(n[a]) +
                       (static_cast<double>(o[a]) - static_cast<double>(o0[a]))) * p.voxel_um;
-        out[3] = static_cast<double>(R) + static_cast<double>(Rc);
+        out[3] = R;
         out[4] = l;
         out[5] = k.c[0];
         out[6] = k.c[1];
@@ -642,7 +637,7 @@ struct WalkerMixed {
 #pragma unroll
             for (int a = 0; a < 3; ++a)
                 out[15 + 3 * q + a] =
-                    (static_cast<double>(ph[q][a]) + static_cast<double>(phc[q][a])) * p.voxel_um;
+                    ph[q][a] * p.voxel_um;
     }
 };
 

@@ -49,7 +49,6 @@ struct RunSetup {
     std::vector<uint32_t> thr;
     double max_sigma = 0.0, max_p = 0.0;
     std::vector<double> gdt;
-    std::vector<float> gdt_f;
     std::vector<double> b_disc, kg, unit;
     std::vector<int> sig_shape;
 };

@@ -45,7 +45,6 @@ struct WalkPlan {
     double voxel_um;
     int n_shapes;
     const double* gdt;   // [n_shapes][n_steps] dt * G_s[i]
-    const float* gdt_f;  // fp32 copy for the mixed form
     double* wstate;      // [n_walkers][kDumpFixed + 3 n_shapes] per-walker results
     void* state;         // [n_walkers] resumable walker states (packed launches), or null
     uint32_t* order;     // [n_slots] walker of each thread slot (kNoWalker: none), or
