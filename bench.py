@@ -225,7 +225,7 @@ def serve(args):
     line = {
         "metric": "served walker-steps/s", "value": agg, "unit": "walker-steps/s",
         "n_gpus": 1, "higher_is_better": True, "data": "synthetic",
-        "dtype": "f32+i32 walk, f64 reductions" if prec == rms.RMS_MIXED else "f64",
+        "dtype": "f32+i32 walk, f64 sums" if prec == rms.RMS_MIXED else "f64",
         "p50_latency_s": float(np.percentile(lat, 50)),
         "p99_latency_s": float(np.percentile(lat, 99)),
         "p50_queue_s": float(np.percentile(queue, 50)),
@@ -371,7 +371,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if prec == rms.RMS_FP64 else "f32+i32 walk, f64 reductions",
+        "dtype": "f64" if prec == rms.RMS_FP64 else "f32+i32 walk, f64 sums",
         "data": "synthetic",
         "config": {"workload": c["name"], "n_walkers": c["n_walkers"], "n_steps": c["n_steps"],
                    "dt_ms": c["dt"], "voxel_um": c["voxel_um"], "n_labels": int(c["D"].size),

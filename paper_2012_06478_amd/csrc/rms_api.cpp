@@ -243,8 +243,7 @@ size_t device_bytes(const RunSetup& r, bool resumable) {
     if (resumable)
         b += static_cast<size_t>(r.n_walkers) *
              walker_state_bytes(r.precision, r.sub->label_bytes, r.n_shapes);
-    else
-        b += order_bytes(r.n_walkers);
+    b += order_bytes(r.n_walkers);
     return b + 64 * 1024;  // allocation granularity slack
 }
 
@@ -278,7 +277,7 @@ int DeviceRun::create(const rms_substrate& sub, const RunSetup& r, bool resumabl
         d_state = st;
     }
     uint32_t* d_order = nullptr;
-    if (!resumable && order_bytes(r.n_walkers) > 0)
+    if (order_bytes(r.n_walkers) > 0)
         RMS_ALLOC(d_order, order_bytes(r.n_walkers) / sizeof(uint32_t));
 #undef RMS_ALLOC
     RMS_HIP(upload(d_sigma, r.sigma, s));

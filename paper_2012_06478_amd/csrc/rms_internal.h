@@ -54,10 +54,11 @@ struct WalkPlan {
 
 constexpr uint32_t kNoWalker = 0xFFFFFFFFu;
 
-// One block of a packed launch: walkers [first_walker, first_walker + kBlock)
-// of plan `plan`, steps [step_begin, step_end).
+// One block of a packed launch: thread slots [first_slot, first_slot + kBlock)
+// of plan `plan` (walker = slot, or plan.order[slot]), steps [step_begin,
+// step_end).
 struct PackedItem {
-    int64_t first_walker;
+    int64_t first_slot;
     int plan;
     uint32_t step_begin, step_end;
     uint32_t pad;

@@ -134,7 +134,11 @@ void rms_server::loop() {
             }
         }
         for (Request* r : admit) {
-            const int rc = r->dev.create(*r->setup.sub, r->setup, true, stream);
+            int rc = r->dev.create(*r->setup.sub, r->setup, true, stream);
+            if (rc == RMS_OK) {
+                const hipError_t eo = rms::launch_order(r->dev.wp, stream);
+                if (eo != hipSuccess) rc = rms::hip_fail("walker order", eo);
+            }
             if (rc != RMS_OK) {
                 finish(r, rc, rms::last_error());
                 continue;
@@ -172,7 +176,15 @@ void rms_server::loop() {
                 const int64_t b = r->steps_done;
                 const int64_t e = std::min(r->setup.n_steps, b + S);
                 step_end[index[r]] = e;
-                for (int64_t w = 0; w < r->setup.n_walkers; w += rms::kBlock)
+                // slot block k of an ordered run belongs on XCD k mod 8: start the
+                // run at a launch block index that is a multiple of 8 (the filler
+                // items' slots lie past the run's slots, so their threads exit)
+                const int64_t n_slots = r->dev.wp.n_slots;
+                if (r->dev.wp.order)
+                    while ((items.size() - first) % 8 != 0)
+                        items.push_back(rms::PackedItem{n_slots, plan, static_cast<uint32_t>(b),
+                                                        static_cast<uint32_t>(e), 0u});
+                for (int64_t w = 0; w < n_slots; w += rms::kBlock)
                     items.push_back(rms::PackedItem{w, plan, static_cast<uint32_t>(b),
                                                     static_cast<uint32_t>(e), 0u});
             }

@@ -51,8 +51,16 @@ __global__ __launch_bounds__(kBlock) RMS_WALK_OCCUPANCY void walk_packed_kernel(
                                                              const WalkPlan* __restrict__ plans) {
     const PackedItem it = items[blockIdx.x];
     const WalkPlan p = plans[it.plan];
-    const int64_t w = it.first_walker + threadIdx.x;
-    if (w >= p.n_walkers) return;
+    const int64_t slot = it.first_slot + threadIdx.x;
+    int64_t w = slot;
+    if (p.order) {
+        if (slot >= p.n_slots) return;
+        const uint32_t o = p.order[slot];
+        if (o == kNoWalker) return;
+        w = o;
+    } else if (w >= p.n_walkers) {
+        return;
+    }
     const LabelT* __restrict__ lab = static_cast<const LabelT*>(p.labels);
     const Ids id{static_cast<uint32_t>(w), static_cast<uint32_t>(w >> 32),
                  static_cast<uint32_t>(p.seed), static_cast<uint32_t>(p.seed >> 32)};
@@ -71,7 +79,8 @@ __global__ __launch_bounds__(kBlock) RMS_WALK_OCCUPANCY void walk_packed_kernel(
 // Walker order.  The walk gathers labels at random places of the volume; a
 // 16 MB volume misses the 4 MB L2 of each XCD.  Blocks are dealt to the eight
 // XCDs round-robin (block b on XCD b mod 8), so the walkers are sorted by the
-// Morton code of their start cell (64 cells per axis), the sorted list is cut
+// Morton code of their start cell (2^cb cells per axis, cb from 1 to 6 so
+// that a cell holds about four walkers), the sorted list is cut
 // into eight equal runs, and run c fills blocks c, c + 8, c + 16, ...: each
 // XCD then walks one compact part of the volume and the lanes of a wave start
 // close together.  A walker's result depends only on its index, so the order
@@ -80,9 +89,14 @@ __global__ __launch_bounds__(kBlock) RMS_WALK_OCCUPANCY void walk_packed_kernel(
 // arbitrary).
 
 constexpr int kXcds = 8;
-constexpr int kCellBits = 6;
-constexpr uint32_t kCells = 1u << (3 * kCellBits);
+constexpr int kMaxCellBits = 6;
 constexpr int kScanThreads = 1024;
+
+int cell_bits(int64_t n) {  // about four walkers per cell
+    int cb = 1;
+    while (cb < kMaxCellBits && (int64_t(4) << (3 * cb)) < n) ++cb;
+    return cb;
+}
 
 int64_t order_chunk(int64_t n) {  // walkers per XCD run, whole blocks
     const int64_t per = (n + kXcds - 1) / kXcds;
@@ -94,19 +108,19 @@ bool order_used(int64_t n) { return n >= 1 && n < static_cast<int64_t>(kNoWalker
 __device__ __forceinline__ uint32_t spread3(uint32_t v) {  // bit i -> bit 3i
     uint32_t r = 0;
 #pragma unroll
-    for (int i = 0; i < kCellBits; ++i) r |= ((v >> i) & 1u) << (3 * i);
+    for (int i = 0; i < kMaxCellBits; ++i) r |= ((v >> i) & 1u) << (3 * i);
     return r;
 }
 
 __global__ __launch_bounds__(kBlock) void order_init_kernel(uint32_t* order, int64_t n_slots,
-                                                            uint32_t* count) {
+                                                            uint32_t* count, uint32_t n_cells) {
     const int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
     if (i < n_slots) order[i] = kNoWalker;
-    if (i < kCells) count[i] = 0u;
+    if (i < n_cells) count[i] = 0u;
 }
 
 __global__ __launch_bounds__(kBlock) void order_keys_kernel(WalkPlan p, uint32_t* count,
-                                                            uint32_t* keys) {
+                                                            uint32_t* keys, int cb) {
     const int64_t w = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
     if (w >= p.n_walkers) return;
     const Ids id{static_cast<uint32_t>(w), static_cast<uint32_t>(w >> 32),
@@ -119,20 +133,24 @@ __global__ __launch_bounds__(kBlock) void order_keys_kernel(WalkPlan p, uint32_t
     uint32_t key = 0;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        const uint32_t c = static_cast<uint32_t>((static_cast<uint64_t>(k.c[a]) << kCellBits) / n[a]);
+        const uint32_t c = static_cast<uint32_t>((static_cast<uint64_t>(k.c[a]) << cb) / n[a]);
         key |= spread3(c) << a;
     }
     keys[w] = key;
     atomicAdd(&count[key], 1u);
 }
 
-// Exclusive prefix sum of the kCells cell counts, in place, by one block.
-__global__ __launch_bounds__(kScanThreads) void order_scan_kernel(uint32_t* count) {
-    constexpr int per = kCells / kScanThreads;
+// Exclusive prefix sum of the n_cells (a power of two) cell counts, in place,
+// by one block: thread t scans entries [t per, (t + 1) per).
+__global__ __launch_bounds__(kScanThreads) void order_scan_kernel(uint32_t* count, uint32_t n_cells) {
+    const uint32_t per = (n_cells + kScanThreads - 1) / kScanThreads;
+    const uint32_t lo = threadIdx.x * per;
+    const uint32_t hi = lo + per < n_cells ? lo + per : n_cells;
+    const uint32_t m = lo < hi ? hi - lo : 0u;
     __shared__ uint32_t part[kScanThreads];
-    uint32_t* c = count + threadIdx.x * per;
+    uint32_t* c = count + lo;
     uint32_t sum = 0;
-    for (int i = 0; i < per; ++i) sum += c[i];
+    for (uint32_t i = 0; i < m; ++i) sum += c[i];
     part[threadIdx.x] = sum;
     __syncthreads();
     for (int off = 1; off < kScanThreads; off <<= 1) {  // inclusive Hillis-Steele scan
@@ -142,7 +160,7 @@ __global__ __launch_bounds__(kScanThreads) void order_scan_kernel(uint32_t* coun
         __syncthreads();
     }
     uint32_t run = part[threadIdx.x] - sum;
-    for (int i = 0; i < per; ++i) {
+    for (uint32_t i = 0; i < m; ++i) {
         const uint32_t v = c[i];
         c[i] = run;
         run += v;
@@ -205,23 +223,26 @@ size_t state_bytes_ns(int ns) {
 
 size_t order_bytes(int64_t n) {
     if (!order_used(n)) return 0;
-    return static_cast<size_t>(kXcds * order_chunk(n) + kCells + n) * sizeof(uint32_t);
+    return static_cast<size_t>(kXcds * order_chunk(n) + (int64_t(1) << (3 * cell_bits(n))) + n) *
+           sizeof(uint32_t);
 }
 
 int64_t order_slots(int64_t n) { return order_used(n) ? kXcds * order_chunk(n) : n; }
 
-// Scratch behind p.order: order[n_slots], count[kCells], keys[n_walkers].
+// Scratch behind p.order: order[n_slots], count[n_cells], keys[n_walkers].
 hipError_t launch_order(const WalkPlan& p, hipStream_t s) {
     if (!p.order) return hipSuccess;
-    uint32_t* count = p.order + p.n_slots;
-    uint32_t* keys = count + kCells;
     const int64_t n = p.n_walkers;
-    const int64_t init = p.n_slots > kCells ? p.n_slots : kCells;
+    const int cb = cell_bits(n);
+    const uint32_t n_cells = 1u << (3 * cb);
+    uint32_t* count = p.order + p.n_slots;
+    uint32_t* keys = count + n_cells;
+    const int64_t init = p.n_slots > n_cells ? p.n_slots : n_cells;
     order_init_kernel<<<dim3(static_cast<unsigned>((init + kBlock - 1) / kBlock)), kBlock, 0, s>>>(
-        p.order, p.n_slots, count);
+        p.order, p.n_slots, count, n_cells);
     const dim3 grid(static_cast<unsigned>((n + kBlock - 1) / kBlock));
-    order_keys_kernel<<<grid, kBlock, 0, s>>>(p, count, keys);
-    order_scan_kernel<<<1, kScanThreads, 0, s>>>(count);
+    order_keys_kernel<<<grid, kBlock, 0, s>>>(p, count, keys, cb);
+    order_scan_kernel<<<1, kScanThreads, 0, s>>>(count, n_cells);
     order_scatter_kernel<<<grid, kBlock, 0, s>>>(keys, count, p.order, n, order_chunk(n));
     return hipGetLastError();
 }
