@@ -33,7 +33,7 @@ extern "C" {
 #define RMS_E_INVALID_ARG (-1)         /* malformed argument (message says which) */
 #define RMS_E_LABEL_RANGE (-2)         /* a voxel label >= n_labels */
 #define RMS_E_STEP_TOO_LARGE (-3)      /* max step length >= voxel size (section 2.1.1) */
-#define RMS_E_PROB_TOO_LARGE (-4)      /* a permeation probability > 0.5 (Table 1: P << 1) */
+#define RMS_E_PROB_TOO_LARGE (-4)      /* a permeation probability > RMS_MAX_PERM_PROB */
 #define RMS_E_UNBALANCED_WAVEFORM (-5) /* |sum_i G_i| > 1e-9 sum_i |G_i| for a shape */
 #define RMS_E_OOM (-6)                 /* device or host allocation failed */
 #define RMS_E_DEVICE (-7)              /* a HIP runtime call failed */
@@ -48,6 +48,9 @@ extern "C" {
 #define RMS_MAX_SHAPES 4     /* gradient waveform shapes per run */
 #define RMS_MAX_SIGNALS 960  /* n_shapes * n_b * n_dirs per run */
 #define RMS_MAX_LABELS 4096  /* compartment labels per substrate */
+/* Largest permeation probability per membrane hit a run accepts (Table 1:
+ * P << 1; rms_result.max_perm_prob reports the largest one a run uses). */
+#define RMS_MAX_PERM_PROB 0.1
 
 /* Per-walker dump record (doubles), in this order:
  *   0-2  displacement x, y, z (um, unwrapped)

@@ -25,6 +25,7 @@ RMS_MIXED = 1
 RMS_MAX_SHAPES = 4
 RMS_MAX_SIGNALS = 960
 RMS_MAX_LABELS = 4096
+RMS_MAX_PERM_PROB = 0.1
 RMS_DUMP_FIXED = 15
 ERROR_NAMES = {
     -1: "RMS_E_INVALID_ARG", -2: "RMS_E_LABEL_RANGE", -3: "RMS_E_STEP_TOO_LARGE",

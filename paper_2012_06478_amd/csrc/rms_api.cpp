@@ -88,10 +88,10 @@ int build_tables(const rms_substrate& sub, const double* D, const double* kappa,
                     const double k0 = k / (1.0 + 0.5 * k * C3 * (ds[a] / D[a] + ds[b] / D[b]));
                     const double P = std::min(1.0, k0 * ds[a] * C3 / D[a]);
                     t.max_p = std::max(t.max_p, P);
-                    if (P > 0.5)
+                    if (P > RMS_MAX_PERM_PROB)
                         return fail(RMS_E_PROB_TOO_LARGE,
                                     "permeation probability " + std::to_string(P) +
-                                        " > 0.5: lower dt or kappa");
+                                        " > RMS_MAX_PERM_PROB (0.1): lower dt or kappa");
                     th = static_cast<uint32_t>(std::floor(std::ldexp(P, 32)));
                 }
             }

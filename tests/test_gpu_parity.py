@@ -247,6 +247,13 @@ def test_errors_reported():
         rms.rms_run(sub, seed=1, n_walkers=10, n_steps=10, dt=2e-4,
                     params=dict(D=[2.0, 2.0], kappa=[[0, 1e4], [1e4, 0]]))
     assert e.value.code == -4
+    with pytest.raises(rms.RmsError) as e:  # P about 0.16: above RMS_MAX_PERM_PROB
+        rms.rms_run(sub, seed=1, n_walkers=10, n_steps=10, dt=2e-4,
+                    params=dict(D=[2.0, 2.0], kappa=[[0, 12.0], [12.0, 0]]))
+    assert e.value.code == -4 and "RMS_MAX_PERM_PROB" in rms.rms_last_error()
+    r = rms.rms_run(sub, seed=1, n_walkers=10, n_steps=10, dt=2e-4,
+                    params=dict(D=[2.0, 2.0], kappa=[[0, 5.0], [5.0, 0]]))
+    assert 0.05 < r["max_perm_prob"] <= rms.RMS_MAX_PERM_PROB
     sub.close()
 
 

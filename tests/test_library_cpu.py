@@ -53,6 +53,8 @@ def test_header_limits_match_binding():
     for name in ("RMS_MAX_SHAPES", "RMS_MAX_SIGNALS", "RMS_MAX_LABELS", "RMS_DUMP_FIXED"):
         v = int(re.search(rf"#define {name} (\d+)", text).group(1))
         assert getattr(rms, name) == v
+    v = float(re.search(r"#define RMS_MAX_PERM_PROB ([0-9.]+)", text).group(1))
+    assert rms.RMS_MAX_PERM_PROB == v
 
 
 _SINCOS_PROBE = r"""
