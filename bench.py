@@ -30,7 +30,8 @@ sys.path.insert(0, ROOT)
 # ideal gfx950 implementation of the method needs:
 OPS_PER_WALKER_STEP = {
     "philox_half_block": 40,  # 10 rounds x (2 mul_lo + 2 mul_hi + 4 xor) / 2 steps per block
-    "direction": 50,          # 2 cvt + 2 fma, v_z, rho (3 + sqrt ~8), sincospi ~33, 2 mul
+    "direction": 36,          # 2 cvt + 2 fma, v_z, rho (3 + sqrt ~8), sincos 2 pi u by
+                              #   table + short series ~19, 2 mul
     "face_events": 12,        # 3 x (gap select 2 + budget x |v| 1 + compare 1)
     "event_order": 13,        # 3 x (cross products mul + fma + compare) + table lookup 4
     "events": 22,             # 0.73 events/step x (neighbour index + wrap ~12, gather, compare,

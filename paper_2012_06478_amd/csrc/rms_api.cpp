@@ -182,6 +182,8 @@ int prepare_run(const rms_substrate* sub, const rms_params* params, uint64_t see
     // discrete b of a unit shape is dt sum_k Q_k^2 (section 2.3, Eq. signal)
     r.b_disc.assign(n_shapes, 0.0);
     std::vector<double> kscale(static_cast<size_t>(n_shapes) * n_b, 0.0);
+    r.trig.resize(2 * kTrigSize);
+    fill_trig_table(r.trig.data());
     r.gdt.assign(static_cast<size_t>(n_shapes) * n_steps, 0.0);
     for (int s = 0; s < n_shapes; ++s) {
         const double* G = waveform + static_cast<size_t>(s) * n_steps;
@@ -235,7 +237,7 @@ int prepare_run(const rms_substrate* sub, const rms_params* params, uint64_t see
 size_t device_bytes(const RunSetup& r, bool resumable) {
     const size_t L = static_cast<size_t>(r.sub->n_labels);
     size_t b = L * (2 * sizeof(double) + 2 * sizeof(float)) + L * L * sizeof(uint32_t);
-    b += r.gdt.size() * sizeof(double);
+    b += r.gdt.size() * sizeof(double) + 2 * kTrigSize * sizeof(double);
     b += static_cast<size_t>(r.n_walkers) * r.width * sizeof(double);
     b += r.kg.size() * sizeof(double) + r.sig_shape.size() * sizeof(int);
     b += static_cast<size_t>(r.n_acc) * r.n_blocks * sizeof(double);
@@ -263,6 +265,8 @@ int DeviceRun::create(const rms_substrate& sub, const RunSetup& r, bool resumabl
     RMS_ALLOC(d_it2_f, L);
     RMS_ALLOC(d_thr, L * L);
     RMS_ALLOC(d_gdt, r.gdt.size());
+    double* d_trig;
+    RMS_ALLOC(d_trig, 2 * kTrigSize);
     RMS_ALLOC(d_wstate, static_cast<size_t>(r.n_walkers) * r.width);
     RMS_ALLOC(d_kg, r.kg.size());
     RMS_ALLOC(d_sig_shape, r.sig_shape.size());
@@ -286,6 +290,7 @@ int DeviceRun::create(const rms_substrate& sub, const RunSetup& r, bool resumabl
     RMS_HIP(upload(d_it2_f, r.inv_t2_f, s));
     RMS_HIP(upload(d_thr, r.thr, s));
     RMS_HIP(upload(d_gdt, r.gdt, s));
+    RMS_HIP(upload(d_trig, r.trig, s));
     RMS_HIP(upload(d_kg, r.kg, s));
     RMS_HIP(upload(d_sig_shape, r.sig_shape, s));
     RMS_HIP(upload(d_dirs, r.unit, s));
@@ -317,6 +322,7 @@ int DeviceRun::create(const rms_substrate& sub, const RunSetup& r, bool resumabl
     wp.voxel_um = sub.voxel_um;
     wp.n_shapes = r.n_shapes;
     wp.gdt = d_gdt;
+    wp.trig = d_trig;
     wp.wstate = d_wstate;
     wp.state = d_state;
     wp.order = d_order;

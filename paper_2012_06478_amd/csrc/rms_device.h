@@ -93,44 +93,28 @@ struct FmaSgpr {
     }
 };
 
-// cos(2 pi u) and sin(2 pi u) for u in [0, 1] to about 1 ulp.  Reduction to a
-// quarter turn is exact: x = 4u, k = rint(x), r = x - k in [-1/2, 1/2], so
-// 2 pi u = k pi/2 + a with a = r pi/2, |a| <= pi/4.  sin a and cos a are the
-// Taylor series of sine and cosine through a^17 and a^18 (the next terms are
-// below 1e-19 on |a| <= pi/4), evaluated by Horner's rule in a^2; the quadrant
-// k mod 4 then permutes and negates them.  `fk` is the fused multiply-add used
-// for the Horner steps (its third operand is a coefficient).
+// cos(2 pi u) and sin(2 pi u) for u = (w + 1/2) 2^-32, within a few ulp.  The
+// top eight bits of w pick the angle A = 2 pi j / 256 from `tab` (cos A, sin
+// A); the rest is a = 2 pi (w mod 2^24 + 1/2) 2^-32 in (0, 2 pi / 256), whose
+// sine and cosine are the Taylor series through a^7 and a^6 (the next terms
+// are below 1e-17 there), evaluated by Horner's rule in a^2; the angle-sum
+// formulas combine the two.  `fk` is the fused multiply-add used for the
+// Horner steps (its third operand is a coefficient).
 template <class Fma>
-__host__ __device__ __forceinline__ void sincos_2pi(double u, double* s_out, double* c_out,
-                                                    Fma fk) {
-    const double x = 4.0 * u;
-    const double k = rint(x);
-    const double a = (x - k) * 1.5707963267948966;  // pi/2
+__host__ __device__ __forceinline__ void sincos_2pi_word(uint32_t w, const double* tab,
+                                                         double* s_out, double* c_out, Fma fk) {
+    const uint32_t j = w >> 24;
+    const double cA = tab[2 * j], sA = tab[2 * j + 1];
+    const double a = (static_cast<double>(w & 0xFFFFFFu) + 0.5) * (6.283185307179586 * 0x1p-32);
     const double z = a * a;
-    // sin a = a sum_k (-1)^k z^k / (2k+1)!,  k = 0..8
-    double ps = fk(z, 1.0 / 355687428096000.0, -1.0 / 1307674368000.0);  // 1/17!, 1/15!
-    ps = fk(z, ps, 1.0 / 6227020800.0);               // 1/13!
-    ps = fk(z, ps, -1.0 / 39916800.0);                // 1/11!
-    ps = fk(z, ps, 1.0 / 362880.0);                   // 1/9!
-    ps = fk(z, ps, -1.0 / 5040.0);                    // 1/7!
-    ps = fk(z, ps, 1.0 / 120.0);                      // 1/5!
-    ps = fk(z, ps, -1.0 / 6.0);                       // 1/3!
+    double ps = fk(z, -1.0 / 5040.0, 1.0 / 120.0);  // sin a = a (1 - z/3! + z^2/5! - z^3/7!)
+    ps = fk(z, ps, -1.0 / 6.0);
     const double sa = fma(a * z, ps, a);
-    // cos a = sum_k (-1)^k z^k / (2k)!,  k = 0..9
-    double pc = fk(z, -1.0 / 6402373705728000.0, 1.0 / 20922789888000.0);  // 1/18!, 1/16!
-    pc = fk(z, pc, -1.0 / 87178291200.0);             // 1/14!
-    pc = fk(z, pc, 1.0 / 479001600.0);                // 1/12!
-    pc = fk(z, pc, -1.0 / 3628800.0);                 // 1/10!
-    pc = fk(z, pc, 1.0 / 40320.0);                    // 1/8!
-    pc = fk(z, pc, -1.0 / 720.0);                     // 1/6!
-    pc = fk(z, pc, 1.0 / 24.0);                       // 1/4!
-    pc = fma(z, pc, -0.5);                            // 1/2!
+    double pc = fk(z, -1.0 / 720.0, 1.0 / 24.0);    // cos a = 1 - z/2! + z^2/4! - z^3/6!
+    pc = fma(z, pc, -0.5);
     const double ca = fma(z, pc, 1.0);
-    const int q = static_cast<int>(k) & 3;
-    const double cs = (q & 1) ? sa : ca;
-    const double sn = (q & 1) ? ca : sa;
-    *c_out = (q == 1 || q == 2) ? -cs : cs;
-    *s_out = (q >= 2) ? -sn : sn;
+    *c_out = fma(cA, ca, -(sA * sa));
+    *s_out = fma(sA, ca, cA * sa);
 }
 
 // sqrt(y) for finite normal y > 0: the hardware reciprocal square root
@@ -275,6 +259,7 @@ __device__ __forceinline__ Start draw_start(const WalkPlan& p, const Ids& id) {
 template <typename LabelT, int NS>
 struct WalkerF64 {
     static constexpr int kShapes = NS > 0 ? NS : 1;
+    static constexpr bool kTrig = true;  // direction from the LDS angle table
     int lin, l, l0;  // linear voxel index, label, label at the start
     uint32_t nface, nhit, nperm;
     double o[3];
@@ -304,11 +289,10 @@ struct WalkerF64 {
     // membrane word m1.
     __device__ __forceinline__ void step(const WalkPlan& p, const LabelT* __restrict__ lab,
                                          uint32_t i0, uint32_t wa, uint32_t wb, uint32_t m1,
-                                         const Ids& id) {
+                                         const Ids& id, const double* trig) {
         const double u1 = unit_open(wa);
-        const double u2 = unit_open(wb);
-        double sn, cs;
-        sincos_2pi(u2, &sn, &cs, FmaSgpr());
+        double sn, cs;  // of 2 pi u2, u2 = unit_open(wb)
+        sincos_2pi_word(wb, trig, &sn, &cs, FmaSgpr());
         const double rho = 2.0 * sqrt_pos(u1 * (1.0 - u1));
         const double v[3] = {rho * cs, rho * sn, 1.0 - 2.0 * u1};
 
@@ -463,6 +447,7 @@ __device__ __forceinline__ float unit_open_f(uint32_t w) {
 template <typename LabelT, int NS>
 struct WalkerMixed {
     static constexpr int kShapes = NS > 0 ? NS : 1;
+    static constexpr bool kTrig = false;  // hardware sine and cosine
     int lin, l, l0;
     uint32_t nface, nhit, nperm;
     int n[3];     // voxels crossed per axis (signed), exact
@@ -493,7 +478,7 @@ struct WalkerMixed {
 
     __device__ __forceinline__ void step(const WalkPlan& p, const LabelT* __restrict__ lab,
                                          uint32_t i0, uint32_t wa, uint32_t wb, uint32_t m1,
-                                         const Ids& id) {
+                                         const Ids& id, const double* trig) {
         // uniform deviates from the top 24 bits of each word: (k + 1/2) 2^-24
         const float u1 = fmaf(static_cast<float>(wa >> 8), 0x1p-24f, 0x1p-25f);
         const float u2 = fmaf(static_cast<float>(wb >> 8), 0x1p-24f, 0x1p-25f);
@@ -647,7 +632,8 @@ struct WalkerMixed {
 // from being interleaved by the scheduler, which would raise register use.
 template <class Walker, typename LabelT>
 __device__ __forceinline__ void walk_range(const WalkPlan& p, const LabelT* __restrict__ lab,
-                                           Walker& W, uint32_t b, uint32_t e, const Ids& id) {
+                                           Walker& W, uint32_t b, uint32_t e, const Ids& id,
+                                           const double* trig) {
     uint4 wd = make_uint4(0, 0, 0, 0), wm = make_uint4(0, 0, 0, 0);
     for (uint32_t i0 = b; i0 < e; ++i0) {
         const bool odd = (i0 & 1u) != 0;
@@ -655,7 +641,7 @@ __device__ __forceinline__ void walk_range(const WalkPlan& p, const LabelT* __re
         const uint32_t q = i0 & 3u;
         if (q == 0 || i0 == b) wm = philox4x32_10(i0 >> 2, 1u, id.wlo, id.whi, id.k0, id.k1);
         const uint32_t m1 = q == 0 ? wm.x : (q == 1 ? wm.y : (q == 2 ? wm.z : wm.w));
-        W.step(p, lab, i0, odd ? wd.z : wd.x, odd ? wd.w : wd.y, m1, id);
+        W.step(p, lab, i0, odd ? wd.z : wd.x, odd ? wd.w : wd.y, m1, id, trig);
     }
 }
 

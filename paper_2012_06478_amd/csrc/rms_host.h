@@ -5,6 +5,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <cmath>
 #include <cstdint>
 #include <string>
 #include <vector>
@@ -28,6 +29,17 @@ struct rms_substrate {
 
 namespace rms {
 
+// (cos, sin) of the angles 2 pi j / kTrigSize, each rounded once from long
+// double: the table of the double-precision direction draw.
+inline void fill_trig_table(double* cs) {
+    const long double two_pi = 6.283185307179586476925286766559005768394L;
+    for (int j = 0; j < kTrigSize; ++j) {
+        const long double t = two_pi * static_cast<long double>(j) / kTrigSize;
+        cs[2 * j] = static_cast<double>(cosl(t));
+        cs[2 * j + 1] = static_cast<double>(sinl(t));
+    }
+}
+
 // Records a failure for rms_last_error() on the calling thread; returns code.
 int fail(int code, const std::string& msg);
 int hip_fail(const char* what, hipError_t e);
@@ -49,6 +61,7 @@ struct RunSetup {
     std::vector<uint32_t> thr;
     double max_sigma = 0.0, max_p = 0.0;
     std::vector<double> gdt;
+    std::vector<double> trig;  // [kTrigSize][2] angle table (fill_trig_table)
     std::vector<double> b_disc, kg, unit;
     std::vector<int> sig_shape;
 };

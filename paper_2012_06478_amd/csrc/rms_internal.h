@@ -45,6 +45,7 @@ struct WalkPlan {
     double voxel_um;
     int n_shapes;
     const double* gdt;   // [n_shapes][n_steps] dt * G_s[i]
+    const double* trig;  // [kTrigSize][2] cos, sin of 2 pi j / kTrigSize (fill_trig_table)
     double* wstate;      // [n_walkers][kDumpFixed + 3 n_shapes] per-walker results
     void* state;         // [n_walkers] resumable walker states (packed launches), or null
     uint32_t* order;     // [n_slots] walker of each thread slot (kNoWalker: none), or
@@ -53,6 +54,9 @@ struct WalkPlan {
 };
 
 constexpr uint32_t kNoWalker = 0xFFFFFFFFu;
+
+// Angles of the direction table: (cos, sin) of 2 pi j / kTrigSize.
+constexpr int kTrigSize = 256;
 
 // One block of a packed launch: thread slots [first_slot, first_slot + kBlock)
 // of plan `plan` (walker = slot, or plan.order[slot]), steps [step_begin,

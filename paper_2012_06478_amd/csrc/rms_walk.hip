@@ -25,8 +25,22 @@ using dev::Ids;
 // four; the mixed walker needs fewer registers and is not affected.
 #define RMS_WALK_OCCUPANCY __attribute__((amdgpu_waves_per_eu(5, 8)))
 
+// The angle table of the double-precision direction draw, copied to LDS by
+// the whole block before any thread leaves (one entry per thread).
+static_assert(kBlock == kTrigSize, "one table entry per thread");
+template <class Walker>
+__device__ __forceinline__ void load_trig(const WalkPlan& p, double* trig) {
+    if constexpr (Walker::kTrig) {
+        trig[2 * threadIdx.x] = p.trig[2 * threadIdx.x];
+        trig[2 * threadIdx.x + 1] = p.trig[2 * threadIdx.x + 1];
+        __syncthreads();
+    }
+}
+
 template <class Walker, typename LabelT>
 __global__ __launch_bounds__(kBlock) RMS_WALK_OCCUPANCY void walk_kernel(WalkPlan p) {
+    __shared__ double trig[Walker::kTrig ? 2 * kTrigSize : 2];
+    load_trig<Walker>(p, trig);
     const int64_t slot = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
     int64_t w = slot;
     if (p.order) {
@@ -42,7 +56,7 @@ __global__ __launch_bounds__(kBlock) RMS_WALK_OCCUPANCY void walk_kernel(WalkPla
                  static_cast<uint32_t>(p.seed), static_cast<uint32_t>(p.seed >> 32)};
     Walker W;
     W.init(p, lab, id);
-    dev::walk_range(p, lab, W, 0u, static_cast<uint32_t>(p.n_steps), id);
+    dev::walk_range(p, lab, W, 0u, static_cast<uint32_t>(p.n_steps), id, trig);
     W.finish(p, p.wstate + w * (kDumpFixed + 3 * p.n_shapes));
 }
 
@@ -51,6 +65,8 @@ __global__ __launch_bounds__(kBlock) RMS_WALK_OCCUPANCY void walk_packed_kernel(
                                                              const WalkPlan* __restrict__ plans) {
     const PackedItem it = items[blockIdx.x];
     const WalkPlan p = plans[it.plan];
+    __shared__ double trig[Walker::kTrig ? 2 * kTrigSize : 2];
+    load_trig<Walker>(p, trig);
     const int64_t slot = it.first_slot + threadIdx.x;
     int64_t w = slot;
     if (p.order) {
@@ -68,7 +84,7 @@ __global__ __launch_bounds__(kBlock) RMS_WALK_OCCUPANCY void walk_packed_kernel(
     Walker W;
     if (it.step_begin == 0) W.init(p, lab, id);
     else W = *st;
-    dev::walk_range(p, lab, W, it.step_begin, it.step_end, id);
+    dev::walk_range(p, lab, W, it.step_begin, it.step_end, id, trig);
     if (it.step_end == static_cast<uint32_t>(p.n_steps))
         W.finish(p, p.wstate + w * (kDumpFixed + 3 * p.n_shapes));
     else
