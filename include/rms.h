@@ -221,8 +221,9 @@ typedef struct {
 /* Create a server on the HIP device current at the call.
  *   mem_budget_bytes  device memory the server may hold for admitted requests
  *                     (0 = 3/4 of the device's free memory);
- *   slice_steps       steps per slice (even, >= 2), or 0 to size each slice to
- *                     about 4e9 walker-steps of the admitted requests. */
+ *   slice_steps       steps per slice (>= 2, rounded up to a multiple of 4), or 0
+ *                     to size each slice to about 4e9 walker-steps of the
+ *                     admitted requests. */
 int rms_server_create(size_t mem_budget_bytes, int slice_steps, rms_server** out);
 
 /* Queue a request; returns at once with its ticket.  Argument errors are

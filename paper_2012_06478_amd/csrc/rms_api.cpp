@@ -246,6 +246,8 @@ size_t device_bytes(const RunSetup& r, bool resumable) {
         b += static_cast<size_t>(r.n_walkers) *
              walker_state_bytes(r.precision, r.sub->label_bytes, r.n_shapes);
     b += order_bytes(r.n_walkers);
+    if (!resumable && seg_state_bytes(r.precision, r.n_shapes, r.n_walkers) > 0)
+        b += seg_state_bytes(r.precision, r.n_shapes, r.n_walkers) + seg_ctl_bytes(r.n_walkers);
     return b + 64 * 1024;  // allocation granularity slack
 }
 
@@ -283,6 +285,12 @@ int DeviceRun::create(const rms_substrate& sub, const RunSetup& r, bool resumabl
     uint32_t* d_order = nullptr;
     if (order_bytes(r.n_walkers) > 0)
         RMS_ALLOC(d_order, order_bytes(r.n_walkers) / sizeof(uint32_t));
+    uint8_t* d_seg_state = nullptr;
+    uint32_t* d_seg_ctl = nullptr;
+    if (!resumable && seg_state_bytes(r.precision, r.n_shapes, r.n_walkers) > 0) {
+        RMS_ALLOC(d_seg_state, seg_state_bytes(r.precision, r.n_shapes, r.n_walkers));
+        RMS_ALLOC(d_seg_ctl, seg_ctl_bytes(r.n_walkers) / sizeof(uint32_t));
+    }
 #undef RMS_ALLOC
     RMS_HIP(upload(d_sigma, r.sigma, s));
     RMS_HIP(upload(d_it2, r.inv_t2, s));
@@ -327,6 +335,8 @@ int DeviceRun::create(const rms_substrate& sub, const RunSetup& r, bool resumabl
     wp.state = d_state;
     wp.order = d_order;
     wp.n_slots = d_order ? order_slots(r.n_walkers) : r.n_walkers;
+    wp.seg_state = d_order ? d_seg_state : nullptr;
+    wp.seg_ctl = d_order ? d_seg_ctl : nullptr;
 
     rp = ReducePlan{};
     rp.wstate = d_wstate;
@@ -545,11 +555,18 @@ int rms_run(const rms_substrate* sub, const rms_params* params, uint64_t seed, i
     std::vector<double> res(r.n_res);
     RMS_HIP(hipMemcpyAsync(res.data(), dr.rp.result, r.n_res * sizeof(double),
                            hipMemcpyDeviceToHost, stream));
+    std::vector<uint32_t> seg_fail(1, 0u);
+    if (dr.wp.seg_ctl)
+        RMS_HIP(hipMemcpyAsync(seg_fail.data(), dr.wp.seg_ctl + rms::kSegErrorWord,
+                               sizeof(uint32_t), hipMemcpyDeviceToHost, stream));
     if (out->walker_dump)
         RMS_HIP(hipMemcpyAsync(out->walker_dump, dr.wp.wstate,
                                static_cast<size_t>(n_walkers) * r.width * sizeof(double),
                                hipMemcpyDeviceToHost, stream));
     RMS_HIP(hipStreamSynchronize(stream));
+    if (seg_fail[0] != 0u)
+        return rms::fail(RMS_E_DEVICE, "walk: a wait for an earlier segment of a walker block "
+                                       "gave up; no result");
     float ms = 0.0f;
     RMS_HIP(hipEventElapsedTime(&ms, ev0, ev1));
     rms::fill_result(r, res.data(), out);

@@ -626,10 +626,13 @@ struct WalkerMixed {
     }
 };
 
-// Steps [b, e) of one walker: direction words two steps per Philox block,
-// first membrane words four steps per block (both blocks computed under
-// wave-uniform branches).  One step per iteration keeps consecutive steps
-// from being interleaved by the scheduler, which would raise register use.
+// Steps [b, e) of one walker, b a multiple of 4 (every caller starts a range
+// at step 0, at a segment of a multiple of 4 steps or at a server slice of a
+// multiple of 4 steps): direction words two steps per Philox block, first
+// membrane words four steps per block, both blocks computed under
+// wave-uniform branches at the step that opens them.  One step per iteration
+// keeps consecutive steps from being interleaved by the scheduler, which
+// would raise register use.
 template <class Walker, typename LabelT>
 __device__ __forceinline__ void walk_range(const WalkPlan& p, const LabelT* __restrict__ lab,
                                            Walker& W, uint32_t b, uint32_t e, const Ids& id,
@@ -637,9 +640,9 @@ __device__ __forceinline__ void walk_range(const WalkPlan& p, const LabelT* __re
     uint4 wd = make_uint4(0, 0, 0, 0), wm = make_uint4(0, 0, 0, 0);
     for (uint32_t i0 = b; i0 < e; ++i0) {
         const bool odd = (i0 & 1u) != 0;
-        if (!odd || i0 == b) wd = philox4x32_10(i0 >> 1, 0u, id.wlo, id.whi, id.k0, id.k1);
+        if (!odd) wd = philox4x32_10(i0 >> 1, 0u, id.wlo, id.whi, id.k0, id.k1);
         const uint32_t q = i0 & 3u;
-        if (q == 0 || i0 == b) wm = philox4x32_10(i0 >> 2, 1u, id.wlo, id.whi, id.k0, id.k1);
+        if (q == 0) wm = philox4x32_10(i0 >> 2, 1u, id.wlo, id.whi, id.k0, id.k1);
         const uint32_t m1 = q == 0 ? wm.x : (q == 1 ? wm.y : (q == 2 ? wm.z : wm.w));
         W.step(p, lab, i0, odd ? wd.z : wd.x, odd ? wd.w : wd.y, m1, id, trig);
     }

@@ -51,12 +51,22 @@ struct WalkPlan {
     uint32_t* order;     // [n_slots] walker of each thread slot (kNoWalker: none), or
                          // null: slot i runs walker i; followed by the ordering scratch
     int64_t n_slots;
+    void* seg_state;     // [n_slots] walker states between segments of the persistent
+                         // walk (slot order), or null: one thread per walker, whole walk
+    uint32_t* seg_ctl;   // [kSegCtlFixed + n_slots / 64] queue heads, wait-failure
+                         // flag, segments finished per wave of 64 slots
 };
 
 constexpr uint32_t kNoWalker = 0xFFFFFFFFu;
 
 // Angles of the direction table: (cos, sin) of 2 pi j / kTrigSize.
 constexpr int kTrigSize = 256;
+
+// Control words of the persistent walk: eight queue heads, then the flag a
+// block sets when a wait for an earlier segment gives up.
+constexpr int kSegQueues = 8;
+constexpr int kSegErrorWord = kSegQueues;
+constexpr int kSegCtlFixed = kSegQueues + 1;
 
 // One block of a packed launch: thread slots [first_slot, first_slot + kBlock)
 // of plan `plan` (walker = slot, or plan.order[slot]), steps [step_begin,
@@ -102,6 +112,9 @@ hipError_t launch_walk_packed(const PackedItem* items, int n_items, const WalkPl
 // memory it needs (0 when the run keeps slot i = walker i), order_slots() the
 // thread slots of the walk launch; launch_order() fills p.order.
 size_t order_bytes(int64_t n_walkers);
+// Device memory of the persistent walk of an ordered run (state + control).
+size_t seg_state_bytes(int precision, int n_shapes, int64_t n_walkers);
+size_t seg_ctl_bytes(int64_t n_walkers);
 int64_t order_slots(int64_t n_walkers);
 hipError_t launch_order(const WalkPlan& p, hipStream_t s);
 // Bytes of one resumable walker state.

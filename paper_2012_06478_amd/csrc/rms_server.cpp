@@ -156,7 +156,7 @@ void rms_server::loop() {
         for (Request* r : active) walkers += r->setup.n_walkers;
         int64_t S = slice_steps;
         if (S <= 0) S = std::max<int64_t>(64, std::min<int64_t>(1 << 20, 4000000000LL / walkers));
-        S += S & 1;
+        S = (S + 3) / 4 * 4;  // slices start on a multiple of 4 steps (both Philox streams)
 
         // one packed launch per (precision, label width, shape count)
         std::map<std::tuple<int, int, int>, std::vector<Request*>> groups;
@@ -275,7 +275,7 @@ int rms_server_create(size_t mem_budget_bytes, int slice_steps, rms_server** out
         return rc;
     }
     s->budget = mem_budget_bytes ? mem_budget_bytes : free_b / 4 * 3;
-    s->slice_steps = slice_steps + (slice_steps & 1);
+    s->slice_steps = (slice_steps + 3) / 4 * 4;
     s->worker = std::thread([s] { s->loop(); });
     *out = s;
     return RMS_OK;
