@@ -484,7 +484,9 @@ struct WalkerMixed {
         const float u2 = fmaf(static_cast<float>(wb >> 8), 0x1p-24f, 0x1p-25f);
         const float cs = __builtin_amdgcn_cosf(u2);  // cos(2 pi u2)
         const float sn = __builtin_amdgcn_sinf(u2);  // sin(2 pi u2)
-        const float rho = 2.0f * __builtin_sqrtf(u1 * (1.0f - u1));
+        // hardware square root (about 1 ulp): u1 (1 - u1) >= 2^-26, far from
+        // the denormal range the library sqrtf guards against
+        const float rho = 2.0f * __builtin_amdgcn_sqrtf(u1 * (1.0f - u1));
         const float v[3] = {rho * cs, rho * sn, fmaf(-2.0f, u1, 1.0f)};
 
         float g[3], m[3];
