@@ -223,13 +223,22 @@ struct LabelBits {
 // entry it ended in: it passed the face at the volume's end along axis a),
 // it moves back by one period along each flagged axis, in the direction
 // opposite to its pass.
-__device__ __forceinline__ int wrap_halo(const WalkPlan& p, int plin, uint32_t flags,
-                                         uint32_t posm) {
-    const int per[3] = {p.nx, p.ny * p.px, p.nz * p.pxy};
+// (Offsets here are in bytes of the padded volume, `bytes` per entry.)
+__device__ __forceinline__ uint32_t wrap_halo(const WalkPlan& p, uint32_t off, uint32_t flags,
+                                              uint32_t posm, int bytes) {
+    const int per[3] = {p.nx * bytes, p.ny * p.px * bytes, p.nz * p.pxy * bytes};
 #pragma unroll
     for (int a = 0; a < 3; ++a)
-        if ((flags >> a) & 1u) plin -= ((posm >> a) & 1u) ? per[a] : -per[a];
-    return plin;
+        if ((flags >> a) & 1u) off -= static_cast<uint32_t>(((posm >> a) & 1u) ? per[a] : -per[a]);
+    return off;
+}
+
+// Entry at byte offset `off` of the padded label volume.  Offsets stay below
+// 2^32 (fewer than 2^31 entries of at most two bytes), so the load takes a
+// 32-bit offset from the volume's base and needs no 64-bit address arithmetic.
+template <typename LabelT>
+__device__ __forceinline__ uint32_t entry(const LabelT* __restrict__ lab, uint32_t off) {
+    return *reinterpret_cast<const LabelT*>(reinterpret_cast<const char*>(lab) + off);
 }
 
 // Start (section 2.2, item 1): uniform over the voxels that are not dead, then
@@ -260,7 +269,8 @@ template <typename LabelT, int NS>
 struct WalkerF64 {
     static constexpr int kShapes = NS > 0 ? NS : 1;
     static constexpr bool kTrig = true;  // direction from the LDS angle table
-    int lin, l, l0;  // linear voxel index, label, label at the start
+    uint32_t lb;     // byte offset of the voxel's entry in the padded volume
+    int l, l0;       // label, label at the start
     uint32_t nface, nhit, nperm;
     double o[3];
     double sig, it2;
@@ -271,11 +281,11 @@ struct WalkerF64 {
     __device__ __forceinline__ void init(const WalkPlan& p, const LabelT* __restrict__ lab,
                                          const Ids& id) {
         const Start s = draw_start(p, id);
-        lin = padded_index(p, s.lin);
+        lb = static_cast<uint32_t>(padded_index(p, s.lin)) * sizeof(LabelT);
         o[0] = unit_open(s.wox);
         o[1] = unit_open(s.woy);
         o[2] = unit_open(s.woz);
-        l = l0 = lab[lin];  // interior: no flags
+        l = l0 = entry(lab, lb);  // interior: no flags
         sig = p.sigma[l];
         it2 = p.inv_t2[l];
         d[0] = d[1] = d[2] = 0.0;
@@ -300,11 +310,11 @@ struct WalkerF64 {
         // inside the budget sig when gap < sig |v|
         double g[3], m[3];
         uint32_t posm = 0, evm = 0;
-        int sst[3];  // padded-volume index step across the face each axis moves toward
+        int sst[3];  // byte step in the padded volume across the face each axis moves toward
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
             const bool pos = v[a] > 0.0;
-            const int st = a == 0 ? 1 : (a == 1 ? p.px : p.pxy);
+            const int st = (a == 0 ? 1 : (a == 1 ? p.px : p.pxy)) * static_cast<int>(sizeof(LabelT));
             sst[a] = pos ? st : -st;
             posm |= pos ? (1u << a) : 0u;
             m[a] = fabs(v[a]);
@@ -318,13 +328,13 @@ struct WalkerF64 {
         // common case), loaded together so the step waits for memory once
         // rather than once per event.
         const int nev0 = nev;
-        uint32_t rsp[3] = {0u, 0u, 0u};
+        uint32_t rsp[3];  // rsp[k] is set, and read, only for k < nev0
         {
-            int c = lin;
+            uint32_t c = lb;
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
-                c += pick(sst, ax[k]);
-                if (k < nev0) rsp[k] = lab[c];
+                c += static_cast<uint32_t>(pick(sst, ax[k]));
+                if (k < nev0) rsp[k] = entry(lab, c);
             }
         }
         bool spec = true;  // no reflection yet: rsp holds the entries of the voxels reached
@@ -344,9 +354,9 @@ struct WalkerF64 {
             if (k < nev) {
                 const int a = ax[k];
                 ++nface;
-                const int nbk = lin + pick(sst, a);
-                uint32_t raw = rsp[k];
-                if (!(spec && k < nev0)) raw = lab[nbk];
+                const uint32_t nbk = lb + static_cast<uint32_t>(pick(sst, a));
+                uint32_t raw = spec && k < nev0 ? rsp[k] : 0u;
+                if (!(spec && k < nev0)) raw = entry(lab, nbk);
                 const int nl = static_cast<int>(raw & LabelBits<LabelT>::kMask);
                 bool cross = true;
                 if (nl != l) {
@@ -375,7 +385,7 @@ struct WalkerF64 {
                 }
                 if (cross) {
                     passed |= 1u << a;
-                    lin = nbk;
+                    lb = nbk;
                     rawc = raw;
                 } else {
                     refl |= 1u << a;
@@ -384,7 +394,8 @@ struct WalkerF64 {
             }
         }
         const uint32_t halo = rawc >> LabelBits<LabelT>::kShift;
-        if (__builtin_expect(halo != 0u, 0)) lin = wrap_halo(p, lin, halo, posm);
+        if (__builtin_expect(halo != 0u, 0))
+            lb = wrap_halo(p, lb, halo, posm, static_cast<int>(sizeof(LabelT)));
         const double lend = fma(tau, sig, P);
         R = fma(p.dt * tau, it2, R);
         // End point per axis from the free end point o + lend v: mirrored about
@@ -411,7 +422,7 @@ struct WalkerF64 {
 
     // Per-walker record (layout of RMS_DUMP_WIDTH in rms.h).
     __device__ __forceinline__ void finish(const WalkPlan& p, double* out) const {
-        const Coords k = volume_coords(p, lin);
+        const Coords k = volume_coords(p, static_cast<int>(lb / sizeof(LabelT)));
         out[0] = d[0] * p.voxel_um;
         out[1] = d[1] * p.voxel_um;
         out[2] = d[2] * p.voxel_um;
@@ -448,7 +459,8 @@ template <typename LabelT, int NS>
 struct WalkerMixed {
     static constexpr int kShapes = NS > 0 ? NS : 1;
     static constexpr bool kTrig = false;  // hardware sine and cosine
-    int lin, l, l0;
+    uint32_t lb;  // byte offset of the voxel's entry in the padded volume
+    int l, l0;
     uint32_t nface, nhit, nperm;
     int n[3];     // voxels crossed per axis (signed), exact
     float o[3];   // offset in the voxel, [0, 1]
@@ -460,12 +472,12 @@ struct WalkerMixed {
     __device__ __forceinline__ void init(const WalkPlan& p, const LabelT* __restrict__ lab,
                                          const Ids& id) {
         const Start s = draw_start(p, id);
-        lin = padded_index(p, s.lin);
+        lb = static_cast<uint32_t>(padded_index(p, s.lin)) * sizeof(LabelT);
         o[0] = o0[0] = unit_open_f(s.wox);
         o[1] = o0[1] = unit_open_f(s.woy);
         o[2] = o0[2] = unit_open_f(s.woz);
         n[0] = n[1] = n[2] = 0;
-        l = l0 = lab[lin];  // interior: no flags
+        l = l0 = entry(lab, lb);  // interior: no flags
         sig = p.sigma_f[l];
         it2 = p.inv_t2_f[l];
         R = 0.0;
@@ -491,11 +503,11 @@ struct WalkerMixed {
 
         float g[3], m[3];
         uint32_t posm = 0, evm = 0;
-        int sst[3];  // padded-volume index step across the face each axis moves toward
+        int sst[3];  // byte step in the padded volume across the face each axis moves toward
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
             const bool pos = v[a] > 0.0f;
-            const int st = a == 0 ? 1 : (a == 1 ? p.px : p.pxy);
+            const int st = (a == 0 ? 1 : (a == 1 ? p.px : p.pxy)) * static_cast<int>(sizeof(LabelT));
             sst[a] = pos ? st : -st;
             posm |= pos ? (1u << a) : 0u;
             m[a] = fabsf(v[a]);
@@ -509,13 +521,13 @@ struct WalkerMixed {
         // common case), loaded together so the step waits for memory once
         // rather than once per event.
         const int nev0 = nev;
-        uint32_t rsp[3] = {0u, 0u, 0u};
+        uint32_t rsp[3];  // rsp[k] is set, and read, only for k < nev0
         {
-            int c = lin;
+            uint32_t c = lb;
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
-                c += pick(sst, ax[k]);
-                if (k < nev0) rsp[k] = lab[c];
+                c += static_cast<uint32_t>(pick(sst, ax[k]));
+                if (k < nev0) rsp[k] = entry(lab, c);
             }
         }
         bool spec = true;  // no reflection yet: rsp holds the entries of the voxels reached
@@ -535,9 +547,9 @@ struct WalkerMixed {
             if (k < nev) {
                 const int a = ax[k];
                 ++nface;
-                const int nbk = lin + pick(sst, a);
-                uint32_t raw = rsp[k];
-                if (!(spec && k < nev0)) raw = lab[nbk];
+                const uint32_t nbk = lb + static_cast<uint32_t>(pick(sst, a));
+                uint32_t raw = spec && k < nev0 ? rsp[k] : 0u;
+                if (!(spec && k < nev0)) raw = entry(lab, nbk);
                 const int nl = static_cast<int>(raw & LabelBits<LabelT>::kMask);
                 bool cross = true;
                 if (nl != l) {
@@ -566,7 +578,7 @@ struct WalkerMixed {
                 }
                 if (cross) {
                     passed |= 1u << a;
-                    lin = nbk;
+                    lb = nbk;
                     rawc = raw;
                 } else {
                     refl |= 1u << a;
@@ -575,7 +587,8 @@ struct WalkerMixed {
             }
         }
         const uint32_t halo = rawc >> LabelBits<LabelT>::kShift;
-        if (__builtin_expect(halo != 0u, 0)) lin = wrap_halo(p, lin, halo, posm);
+        if (__builtin_expect(halo != 0u, 0))
+            lb = wrap_halo(p, lb, halo, posm, static_cast<int>(sizeof(LabelT)));
         const float lend = fmaf(tau, sig, P);
         R += static_cast<double>(static_cast<float>(p.dt) * tau * it2);
 #pragma unroll
@@ -602,7 +615,7 @@ struct WalkerMixed {
     }
 
     __device__ __forceinline__ void finish(const WalkPlan& p, double* out) const {
-        const Coords k = volume_coords(p, lin);
+        const Coords k = volume_coords(p, static_cast<int>(lb / sizeof(LabelT)));
 #pragma unroll
         for (int a = 0; a < 3; ++a)
             out[a] = (static_cast<double>(n[a]) +
