@@ -76,9 +76,9 @@ __device__ __forceinline__ uint4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_
     return make_uint4(c0, c1, c2, c3);
 }
 
-// (w + 1/2) 2^-32, exact in double
+// (w + 1/2) 2^-32, exact in double (both steps are exact)
 __device__ __forceinline__ double unit_open(uint32_t w) {
-    return fma(static_cast<double>(w), 0x1p-32, 0x1p-33);
+    return (static_cast<double>(w) + 0.5) * 0x1p-32;
 }
 
 // fma(a, b, k) with the constant k taken from a scalar register pair: written
@@ -233,6 +233,14 @@ __device__ __forceinline__ uint32_t wrap_halo(const WalkPlan& p, uint32_t off, u
     return off;
 }
 
+// Permeation threshold from label l into label nl (both below 4096, so the
+// byte offset 4 (l L + nl) fits 32 bits and l L is a 24-bit multiply).
+__device__ __forceinline__ uint32_t threshold(const WalkPlan& p, int l, int nl) {
+    const uint32_t off = (__umul24(static_cast<uint32_t>(l), static_cast<uint32_t>(p.n_labels)) +
+                          static_cast<uint32_t>(nl)) * 4u;
+    return *reinterpret_cast<const uint32_t*>(reinterpret_cast<const char*>(p.thr) + off);
+}
+
 // Entry at byte offset `off` of the padded label volume.  Offsets stay below
 // 2^32 (fewer than 2^31 entries of at most two bytes), so the load takes a
 // 32-bit offset from the volume's base and needs no 64-bit address arithmetic.
@@ -355,8 +363,9 @@ struct WalkerF64 {
                 const int a = ax[k];
                 ++nface;
                 const uint32_t nbk = lb + static_cast<uint32_t>(pick(sst, a));
-                uint32_t raw = spec && k < nev0 ? rsp[k] : 0u;
-                if (!(spec && k < nev0)) raw = entry(lab, nbk);
+                uint32_t raw;
+                if (spec && k < nev0) raw = rsp[k];
+                else raw = entry(lab, nbk);
                 const int nl = static_cast<int>(raw & LabelBits<LabelT>::kMask);
                 bool cross = true;
                 if (nl != l) {
@@ -364,7 +373,7 @@ struct WalkerF64 {
                     if (mw_used == 1) mw = philox4x32_10(i0, 3u, id.wlo, id.whi, id.k0, id.k1);
                     const uint32_t word = mw_used == 0 ? m1 : (mw_used == 1 ? mw.x : mw.y);
                     ++mw_used;
-                    cross = word < p.thr[l * p.n_labels + nl];
+                    cross = word < threshold(p, l, nl);
                     if (cross) {
                         ++nperm;
                         const double ek = fmax(face_len(a), P);
@@ -548,8 +557,9 @@ struct WalkerMixed {
                 const int a = ax[k];
                 ++nface;
                 const uint32_t nbk = lb + static_cast<uint32_t>(pick(sst, a));
-                uint32_t raw = spec && k < nev0 ? rsp[k] : 0u;
-                if (!(spec && k < nev0)) raw = entry(lab, nbk);
+                uint32_t raw;
+                if (spec && k < nev0) raw = rsp[k];
+                else raw = entry(lab, nbk);
                 const int nl = static_cast<int>(raw & LabelBits<LabelT>::kMask);
                 bool cross = true;
                 if (nl != l) {
@@ -557,7 +567,7 @@ struct WalkerMixed {
                     if (mw_used == 1) mw = philox4x32_10(i0, 3u, id.wlo, id.whi, id.k0, id.k1);
                     const uint32_t word = mw_used == 0 ? m1 : (mw_used == 1 ? mw.x : mw.y);
                     ++mw_used;
-                    cross = word < p.thr[l * p.n_labels + nl];
+                    cross = word < threshold(p, l, nl);
                     if (cross) {
                         ++nperm;
                         const float ek = fmaxf(face_len(a), P);
