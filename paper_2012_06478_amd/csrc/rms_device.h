@@ -145,17 +145,20 @@ __device__ __forceinline__ uint32_t div_magic(uint32_t n, uint32_t m, uint32_t s
 
 // Order in which a step reaches the faces of its three axes, by multiplying
 // only: axis a reaches its face after path length e_a = g_a / m_a (g_a >= 0 the
-// gap to the face, m_a = |v_a| > 0), and e_a < e_b exactly when
-// g_a m_b < g_b m_a.  The sign of fma(g_a, m_b, -g_b m_a) decides each of the
-// three pairs; the three bits (e0<e1, e0<e2, e1<e2) index the permutation that
-// sorts (e_0, e_1, e_2), stored as 2-bit fields of two constants.  Patterns no
-// order gives (reachable only by rounding at near-ties) map to (0, 1, 2).
+// gap to the face, m_a = |v_a| > 0), and e_a <= e_b exactly when
+// g_a m_b <= g_b m_a.  For each pair i < j the sign of fma(g_i, m_j, -g_j m_i)
+// decides whether i comes first (ties go to the lower axis, as when the nearest
+// face is taken with x < y < z on ties: a walker left exactly on two faces by a
+// corner reflection has two zero gaps); the three bits (0 before 1, 0 before 2,
+// 1 before 2) index the permutation, stored as 2-bit fields of two constants.
+// Patterns no order gives (reachable only by rounding at near-ties) map to
+// (0, 1, 2).
 template <typename Real>
 __host__ __device__ __forceinline__ void event_order(const Real g[3], const Real m[3], int ax[3]) {
-    const auto lt = [&](int i, int j) -> uint32_t {
-        return fma(g[i], m[j], -(g[j] * m[i])) < Real(0) ? 1u : 0u;
+    const auto first = [&](int i, int j) -> uint32_t {
+        return fma(g[i], m[j], -(g[j] * m[i])) <= Real(0) ? 1u : 0u;
     };
-    const uint32_t sh = 2u * (lt(0, 1) | (lt(0, 2) << 1) | (lt(1, 2) << 2));
+    const uint32_t sh = 2u * (first(0, 1) | (first(0, 2) << 1) | (first(1, 2) << 2));
     constexpr uint32_t kFirst = 0x110Au;   // first axis for patterns 0..7: 2 2 0 0 1 0 1 0
     constexpr uint32_t kSecond = 0x4691u;  // second axis:                  1 0 1 2 2 1 0 1
     ax[0] = static_cast<int>((kFirst >> sh) & 3u);

@@ -134,9 +134,30 @@ long check(std::mt19937_64& g, long n) {
     }
     return bad;
 }
+// exact ties (zero gaps, equal ratios) must keep the lower axis first
+template <typename Real>
+long ties() {
+    long bad = 0;
+    const Real gs[4] = {Real(0), Real(0.25), Real(0.5), Real(0.75)};
+    for (int mask = 0; mask < 64; ++mask) {
+        Real gg[3], m[3];
+        for (int a = 0; a < 3; ++a) {
+            gg[a] = gs[(mask >> (2 * a)) & 3];
+            m[a] = Real(0.5);  // equal |v|: equal gaps are exact ties
+        }
+        int ax[3];
+        rms::dev::event_order(gg, m, ax);
+        for (int k = 0; k < 2; ++k) {
+            const Real ek = gg[ax[k]], en = gg[ax[k + 1]];
+            if (ek > en || (ek == en && ax[k] > ax[k + 1])) ++bad;
+        }
+    }
+    return bad;
+}
 int main() {
     std::mt19937_64 g(7);
-    std::printf("%ld %ld\n", check<double>(g, 1000000), check<float>(g, 1000000));
+    std::printf("%ld %ld %ld %ld\n", check<double>(g, 1000000), check<float>(g, 1000000),
+                ties<double>(), ties<float>());
     return 0;
 }
 """
@@ -145,8 +166,9 @@ int main() {
 def test_device_event_order(tmp_path):
     """The walker's division-free order of a step's face events (pairwise
     cross-multiplied comparisons indexing a permutation table) against sorting
-    the path lengths gap / |v| in long double, on the host build of the same
-    function, for both precision forms."""
+    the path lengths gap / |v| in long double, and exact ties (zero gaps,
+    equal ratios) kept in axis order, on the host build of the same function,
+    for both precision forms."""
     import shutil
     import subprocess
     if shutil.which("hipcc") is None:
@@ -160,4 +182,4 @@ def test_device_event_order(tmp_path):
                           stdout=subprocess.DEVNULL, stderr=subprocess.DEVNULL, timeout=300)
     out = subprocess.run([str(exe)], capture_output=True, text=True, check=True,
                          timeout=120).stdout.split()
-    assert out == ["0", "0"], out
+    assert out == ["0", "0", "0", "0"], out
