@@ -280,6 +280,7 @@ template <typename LabelT, int NS>
 struct WalkerF64 {
     static constexpr int kShapes = NS > 0 ? NS : 1;
     static constexpr bool kTrig = true;  // direction from the LDS angle table
+    static constexpr int kWaves = 5;     // waves per SIMD the persistent walk asks for
     uint32_t lb;     // byte offset of the voxel's entry in the padded volume
     int l, l0;       // label, label at the start
     uint32_t nface, nhit, nperm;
@@ -471,6 +472,7 @@ template <typename LabelT, int NS>
 struct WalkerMixed {
     static constexpr int kShapes = NS > 0 ? NS : 1;
     static constexpr bool kTrig = false;  // hardware sine and cosine
+    static constexpr int kWaves = 6;      // waves per SIMD the persistent walk asks for
     uint32_t lb;  // byte offset of the voxel's entry in the padded volume
     int l, l0;
     uint32_t nface, nhit, nperm;

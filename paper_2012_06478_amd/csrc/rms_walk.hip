@@ -233,7 +233,7 @@ __global__ __launch_bounds__(kBlock) void seg_init_kernel(uint32_t* ctl, int64_t
 }
 
 template <class Walker, typename LabelT>
-__global__ __launch_bounds__(kBlock) RMS_WALK_OCCUPANCY void walk_seg_kernel(
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(Walker::kWaves, 8))) void walk_seg_kernel(
     WalkPlan p, uint32_t n_seg, uint32_t seg_steps, uint32_t waves_per_queue) {
     __shared__ double trig[Walker::kTrig ? 2 * kTrigSize : 2];
     load_trig<Walker>(p, trig);  // the only block barrier, before the loop
@@ -385,12 +385,17 @@ size_t order_bytes(int64_t n) {
 
 int64_t order_slots(int64_t n) { return order_used(n) ? kXcds * order_chunk(n) : n; }
 
-// The double-precision form only: its walker fits five waves per SIMD either
-// way, while the persistent loop costs the mixed walker its sixth wave (on
-// the 1e7-walker axon bundle the mixed form is 11% slower persistent, the
-// fp64 form 4% faster).
+// Which ordered runs take the persistent walk.  The fp64 walker holds five
+// waves per SIMD either way, and the persistent walk is faster at every size
+// measured.  The mixed walker keeps six waves in the persistent loop only with
+// a small spill: that pays while the tail is a large share of the launch (5%
+// faster at 1e6 walkers, 2.5 rounds of resident waves) but not for long
+// launches (3% slower at 1e7 walkers), so the mixed form takes it up to eight
+// rounds of its 6 x 1024 resident waves.
+constexpr int64_t kMixedSegMaxWalkers = int64_t(8) * 6 * 1024 * 64;
+
 size_t seg_state_bytes(int precision, int n_shapes, int64_t n) {
-    if (precision != RMS_FP64 || !order_used(n)) return 0;
+    if (!order_used(n) || (precision != RMS_FP64 && n > kMixedSegMaxWalkers)) return 0;
     return static_cast<size_t>(order_slots(n)) * walker_state_bytes(precision, 2, n_shapes);
 }
 
@@ -420,9 +425,13 @@ hipError_t launch_order(const WalkPlan& p, hipStream_t s) {
 hipError_t launch_walk(const WalkPlan& p, int precision, hipStream_t s) {
     if (p.n_walkers <= 0) return hipSuccess;
     const bool u8 = p.label_bytes == 1;
-    if (precision == RMS_FP64 && p.order && p.seg_state && p.seg_ctl)  // see seg_state_bytes
-        return u8 ? run_seg_ns<dev::WalkerF64, uint8_t>(p, s)
-                  : run_seg_ns<dev::WalkerF64, uint16_t>(p, s);
+    if (p.order && p.seg_state && p.seg_ctl) {
+        if (precision == RMS_FP64)
+            return u8 ? run_seg_ns<dev::WalkerF64, uint8_t>(p, s)
+                      : run_seg_ns<dev::WalkerF64, uint16_t>(p, s);
+        return u8 ? run_seg_ns<dev::WalkerMixed, uint8_t>(p, s)
+                  : run_seg_ns<dev::WalkerMixed, uint16_t>(p, s);
+    }
     if (precision == RMS_FP64)
         return u8 ? run_ns<dev::WalkerF64, uint8_t>(p, s) : run_ns<dev::WalkerF64, uint16_t>(p, s);
     return u8 ? run_ns<dev::WalkerMixed, uint8_t>(p, s) : run_ns<dev::WalkerMixed, uint16_t>(p, s);
