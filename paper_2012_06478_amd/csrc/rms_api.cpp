@@ -113,15 +113,6 @@ void div_magic(uint32_t d, uint32_t* m, uint32_t* sh) {
 }
 
 template <typename T>
-hipError_t dev_alloc(DeviceRun& d, T** p, size_t count) {
-    void* q = nullptr;
-    const hipError_t e = hipMallocAsync(&q, std::max<size_t>(count, 1) * sizeof(T), d.s);
-    if (e == hipSuccess) d.ptrs.push_back(q);
-    *p = static_cast<T*>(q);
-    return e;
-}
-
-template <typename T>
 hipError_t upload(T* dst, const std::vector<T>& src, hipStream_t s) {
     if (src.empty()) return hipSuccess;
     return hipMemcpyAsync(dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice, s);
@@ -255,43 +246,59 @@ int DeviceRun::create(const rms_substrate& sub, const RunSetup& r, bool resumabl
                       hipStream_t stream) {
     s = stream;
     const size_t L = static_cast<size_t>(sub.n_labels);
-    double *d_sigma, *d_it2, *d_gdt, *d_wstate, *d_kg, *d_partial, *d_sums, *d_res, *d_dirs;
-    float *d_sigma_f, *d_it2_f;
-    uint32_t* d_thr;
-    int* d_sig_shape;
-    void* d_state = nullptr;
-#define RMS_ALLOC(ptr, n) RMS_HIP(dev_alloc(*this, &ptr, (n)))
-    RMS_ALLOC(d_sigma, L);
-    RMS_ALLOC(d_it2, L);
-    RMS_ALLOC(d_sigma_f, L);
-    RMS_ALLOC(d_it2_f, L);
-    RMS_ALLOC(d_thr, L * L);
-    RMS_ALLOC(d_gdt, r.gdt.size());
-    double* d_trig;
-    RMS_ALLOC(d_trig, 2 * kTrigSize);
-    RMS_ALLOC(d_wstate, static_cast<size_t>(r.n_walkers) * r.width);
-    RMS_ALLOC(d_kg, r.kg.size());
-    RMS_ALLOC(d_sig_shape, r.sig_shape.size());
-    RMS_ALLOC(d_partial, static_cast<size_t>(r.n_acc) * r.n_blocks);
-    RMS_ALLOC(d_sums, r.n_acc);
-    RMS_ALLOC(d_res, r.n_res);
-    RMS_ALLOC(d_dirs, r.unit.size());
-    if (resumable) {
-        uint8_t* st = nullptr;
-        RMS_ALLOC(st, static_cast<size_t>(r.n_walkers) *
-                          walker_state_bytes(r.precision, sub.label_bytes, r.n_shapes));
-        d_state = st;
-    }
-    uint32_t* d_order = nullptr;
-    if (order_bytes(r.n_walkers) > 0)
-        RMS_ALLOC(d_order, order_bytes(r.n_walkers) / sizeof(uint32_t));
-    uint8_t* d_seg_state = nullptr;
-    uint32_t* d_seg_ctl = nullptr;
-    if (!resumable && seg_state_bytes(r.precision, r.n_shapes, r.n_walkers) > 0) {
-        RMS_ALLOC(d_seg_state, seg_state_bytes(r.precision, r.n_shapes, r.n_walkers));
-        RMS_ALLOC(d_seg_ctl, seg_ctl_bytes(r.n_walkers) / sizeof(uint32_t));
-    }
-#undef RMS_ALLOC
+    // One device allocation for the whole run, carved into 256-byte aligned
+    // pieces (an allocation and a free per buffer cost about 90 us each).
+    size_t total = 0;
+    const auto take = [&total](size_t bytes) {
+        const size_t off = total;
+        total += (std::max<size_t>(bytes, 1) + 255) / 256 * 256;
+        return off;
+    };
+    const size_t o_sigma = take(L * sizeof(double));
+    const size_t o_it2 = take(L * sizeof(double));
+    const size_t o_sigma_f = take(L * sizeof(float));
+    const size_t o_it2_f = take(L * sizeof(float));
+    const size_t o_thr = take(L * L * sizeof(uint32_t));
+    const size_t o_gdt = take(r.gdt.size() * sizeof(double));
+    const size_t o_trig = take(2 * kTrigSize * sizeof(double));
+    const size_t o_wstate = take(static_cast<size_t>(r.n_walkers) * r.width * sizeof(double));
+    const size_t o_kg = take(r.kg.size() * sizeof(double));
+    const size_t o_sig_shape = take(r.sig_shape.size() * sizeof(int));
+    const size_t o_partial = take(static_cast<size_t>(r.n_acc) * r.n_blocks * sizeof(double));
+    const size_t o_sums = take(static_cast<size_t>(r.n_acc) * sizeof(double));
+    const size_t o_res = take(static_cast<size_t>(r.n_res) * sizeof(double));
+    const size_t o_dirs = take(r.unit.size() * sizeof(double));
+    const size_t state_b = resumable ? static_cast<size_t>(r.n_walkers) *
+                                           walker_state_bytes(r.precision, sub.label_bytes, r.n_shapes)
+                                     : 0;
+    const size_t o_state = take(state_b);
+    const size_t order_b = order_bytes(r.n_walkers);
+    const size_t o_order = take(order_b);
+    const size_t seg_b = resumable ? 0 : seg_state_bytes(r.precision, r.n_shapes, r.n_walkers);
+    const size_t o_seg_state = take(seg_b);
+    const size_t o_seg_ctl = take(seg_b > 0 ? seg_ctl_bytes(r.n_walkers) : 0);
+    void* base = nullptr;
+    RMS_HIP(hipMallocAsync(&base, total, s));
+    ptrs.push_back(base);
+    uint8_t* const b = static_cast<uint8_t*>(base);
+    double* d_sigma = reinterpret_cast<double*>(b + o_sigma);
+    double* d_it2 = reinterpret_cast<double*>(b + o_it2);
+    float* d_sigma_f = reinterpret_cast<float*>(b + o_sigma_f);
+    float* d_it2_f = reinterpret_cast<float*>(b + o_it2_f);
+    uint32_t* d_thr = reinterpret_cast<uint32_t*>(b + o_thr);
+    double* d_gdt = reinterpret_cast<double*>(b + o_gdt);
+    double* d_trig = reinterpret_cast<double*>(b + o_trig);
+    double* d_wstate = reinterpret_cast<double*>(b + o_wstate);
+    double* d_kg = reinterpret_cast<double*>(b + o_kg);
+    int* d_sig_shape = reinterpret_cast<int*>(b + o_sig_shape);
+    double* d_partial = reinterpret_cast<double*>(b + o_partial);
+    double* d_sums = reinterpret_cast<double*>(b + o_sums);
+    double* d_res = reinterpret_cast<double*>(b + o_res);
+    double* d_dirs = reinterpret_cast<double*>(b + o_dirs);
+    void* d_state = state_b ? static_cast<void*>(b + o_state) : nullptr;
+    uint32_t* d_order = order_b ? reinterpret_cast<uint32_t*>(b + o_order) : nullptr;
+    uint8_t* d_seg_state = seg_b ? b + o_seg_state : nullptr;
+    uint32_t* d_seg_ctl = seg_b ? reinterpret_cast<uint32_t*>(b + o_seg_ctl) : nullptr;
     RMS_HIP(upload(d_sigma, r.sigma, s));
     RMS_HIP(upload(d_it2, r.inv_t2, s));
     RMS_HIP(upload(d_sigma_f, r.sigma_f, s));

@@ -100,13 +100,12 @@ __global__ __launch_bounds__(kBlock) RMS_WALK_OCCUPANCY void walk_packed_kernel(
 // into eight equal runs, and run c fills blocks c, c + 8, c + 16, ...: each
 // XCD then walks one compact part of the volume and the lanes of a wave start
 // close together.  A walker's result depends only on its index, so the order
-// changes no result.  Counting sort: cell histogram, one-block scan, scatter
+// changes no result.  Counting sort: cell histogram, two-level scan, scatter
 // with atomic slot counters (the order of walkers inside one cell is
 // arbitrary).
 
 constexpr int kXcds = 8;
 constexpr int kMaxCellBits = 6;
-constexpr int kScanThreads = 1024;
 
 int cell_bits(int64_t n) {  // about four walkers per cell
     int cb = 1;
@@ -156,39 +155,54 @@ __global__ __launch_bounds__(kBlock) void order_keys_kernel(WalkPlan p, uint32_t
     atomicAdd(&count[key], 1u);
 }
 
-// Exclusive prefix sum of the n_cells (a power of two) cell counts, in place,
-// by one block: thread t scans entries [t per, (t + 1) per).
-__global__ __launch_bounds__(kScanThreads) void order_scan_kernel(uint32_t* count, uint32_t n_cells) {
-    const uint32_t per = (n_cells + kScanThreads - 1) / kScanThreads;
-    const uint32_t lo = threadIdx.x * per;
-    const uint32_t hi = lo + per < n_cells ? lo + per : n_cells;
-    const uint32_t m = lo < hi ? hi - lo : 0u;
-    __shared__ uint32_t part[kScanThreads];
-    uint32_t* c = count + lo;
-    uint32_t sum = 0;
-    for (uint32_t i = 0; i < m; ++i) sum += c[i];
-    part[threadIdx.x] = sum;
+// Exclusive prefix sum of the n_cells cell counts in two levels: each block
+// of kScanChunk threads scans one chunk of counts in LDS (in place, within
+// the chunk) and writes the chunk's total; one block then scans the totals,
+// which the scatter adds to the position inside the chunk.
+constexpr uint32_t kScanChunk = 1024;
+constexpr uint32_t kMaxChunks = (1u << (3 * kMaxCellBits)) / kScanChunk;
+
+template <uint32_t N>
+__device__ __forceinline__ uint32_t block_inclusive_scan(uint32_t* part, uint32_t v) {
+    part[threadIdx.x] = v;
     __syncthreads();
-    for (int off = 1; off < kScanThreads; off <<= 1) {  // inclusive Hillis-Steele scan
-        const uint32_t v = threadIdx.x >= static_cast<unsigned>(off) ? part[threadIdx.x - off] : 0u;
+    for (uint32_t off = 1; off < N; off <<= 1) {  // Hillis-Steele
+        const uint32_t u = threadIdx.x >= off ? part[threadIdx.x - off] : 0u;
         __syncthreads();
-        part[threadIdx.x] += v;
+        part[threadIdx.x] += u;
         __syncthreads();
     }
-    uint32_t run = part[threadIdx.x] - sum;
-    for (uint32_t i = 0; i < m; ++i) {
-        const uint32_t v = c[i];
-        c[i] = run;
-        run += v;
-    }
+    return part[threadIdx.x];
+}
+
+__global__ __launch_bounds__(kScanChunk) void order_scan_chunks_kernel(uint32_t* count,
+                                                                       uint32_t n_cells,
+                                                                       uint32_t* totals) {
+    __shared__ uint32_t part[kScanChunk];
+    const uint32_t i = blockIdx.x * kScanChunk + threadIdx.x;
+    const uint32_t v = i < n_cells ? count[i] : 0u;
+    const uint32_t inc = block_inclusive_scan<kScanChunk>(part, v);
+    if (i < n_cells) count[i] = inc - v;
+    if (threadIdx.x == kScanChunk - 1) totals[blockIdx.x] = inc;
+}
+
+__global__ __launch_bounds__(kMaxChunks) void order_scan_totals_kernel(uint32_t* totals,
+                                                                       uint32_t n_chunks) {
+    __shared__ uint32_t part[kMaxChunks];
+    const uint32_t v = threadIdx.x < n_chunks ? totals[threadIdx.x] : 0u;
+    const uint32_t inc = block_inclusive_scan<kMaxChunks>(part, v);
+    if (threadIdx.x < n_chunks) totals[threadIdx.x] = inc - v;
 }
 
 __global__ __launch_bounds__(kBlock) void order_scatter_kernel(const uint32_t* keys, uint32_t* next,
+                                                               const uint32_t* totals,
                                                                uint32_t* order, int64_t n,
                                                                int64_t chunk) {
     const int64_t w = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
     if (w >= n) return;
-    const int64_t pos = atomicAdd(&next[keys[w]], 1u);  // place in the sorted list
+    const uint32_t key = keys[w];
+    const int64_t pos = static_cast<int64_t>(atomicAdd(&next[key], 1u)) +
+                        totals[key / kScanChunk];  // place in the sorted list
     const int64_t c = pos / chunk, j = pos - c * chunk;
     order[((j / kBlock) * kXcds + c) * kBlock + j % kBlock] = static_cast<uint32_t>(w);
 }
@@ -379,7 +393,8 @@ size_t state_bytes_ns(int ns) {
 
 size_t order_bytes(int64_t n) {
     if (!order_used(n)) return 0;
-    return static_cast<size_t>(kXcds * order_chunk(n) + (int64_t(1) << (3 * cell_bits(n))) + n) *
+    return static_cast<size_t>(kXcds * order_chunk(n) + (int64_t(1) << (3 * cell_bits(n))) + n +
+                               kMaxChunks) *
            sizeof(uint32_t);
 }
 
@@ -404,7 +419,8 @@ size_t seg_ctl_bytes(int64_t n) {
     return static_cast<size_t>(kSegCtlFixed + order_slots(n) / kWave) * sizeof(uint32_t);
 }
 
-// Scratch behind p.order: order[n_slots], count[n_cells], keys[n_walkers].
+// Scratch behind p.order: order[n_slots], count[n_cells], keys[n_walkers],
+// totals[kMaxChunks].
 hipError_t launch_order(const WalkPlan& p, hipStream_t s) {
     if (!p.order) return hipSuccess;
     const int64_t n = p.n_walkers;
@@ -412,13 +428,16 @@ hipError_t launch_order(const WalkPlan& p, hipStream_t s) {
     const uint32_t n_cells = 1u << (3 * cb);
     uint32_t* count = p.order + p.n_slots;
     uint32_t* keys = count + n_cells;
+    uint32_t* totals = keys + n;
+    const uint32_t n_chunks = (n_cells + kScanChunk - 1) / kScanChunk;
     const int64_t init = p.n_slots > n_cells ? p.n_slots : n_cells;
     order_init_kernel<<<dim3(static_cast<unsigned>((init + kBlock - 1) / kBlock)), kBlock, 0, s>>>(
         p.order, p.n_slots, count, n_cells);
     const dim3 grid(static_cast<unsigned>((n + kBlock - 1) / kBlock));
     order_keys_kernel<<<grid, kBlock, 0, s>>>(p, count, keys, cb);
-    order_scan_kernel<<<1, kScanThreads, 0, s>>>(count, n_cells);
-    order_scatter_kernel<<<grid, kBlock, 0, s>>>(keys, count, p.order, n, order_chunk(n));
+    order_scan_chunks_kernel<<<n_chunks, kScanChunk, 0, s>>>(count, n_cells, totals);
+    order_scan_totals_kernel<<<1, kMaxChunks, 0, s>>>(totals, n_chunks);
+    order_scatter_kernel<<<grid, kBlock, 0, s>>>(keys, count, totals, p.order, n, order_chunk(n));
     return hipGetLastError();
 }
 
