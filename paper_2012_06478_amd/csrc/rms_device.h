@@ -136,6 +136,16 @@ struct Ids {
     uint32_t wlo, whi, k0, k1;
 };
 
+// Block of substream 3 for step index i0: the second and third membrane words
+// of the step.  Few steps hit a membrane twice, so the block is computed only
+// on that branch; the empty asm on the counter keeps the compiler from
+// evaluating the ten rounds speculatively on every step.
+__device__ __forceinline__ uint4 rare_block(uint32_t i0, const Ids& id) {
+    uint32_t c = i0;
+    asm volatile("" : "+v"(c));
+    return philox4x32_10(c, 3u, id.wlo, id.whi, id.k0, id.k1);
+}
+
 // n / d for n < 2^31 as (n m) >> sh with m = ceil(2^sh / d), sh = 31 +
 // ceil(log2 d): exact, because the error n (m - 2^sh/d) / 2^sh stays below
 // 2^-ceil(log2 d) <= 1/d.  m and sh come from the host.
@@ -360,7 +370,7 @@ struct WalkerF64 {
         uint32_t passed = 0, refl = 0;
         uint32_t rawc = 0;  // entry of the voxel last passed into (its halo flags)
         int mw_used = 0;
-        uint4 mw = make_uint4(0, 0, 0, 0);
+        uint4 mw;  // words of substream 3, computed before the second membrane hit reads them
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
             if (k < nev) {
@@ -374,7 +384,7 @@ struct WalkerF64 {
                 bool cross = true;
                 if (nl != l) {
                     ++nhit;
-                    if (mw_used == 1) mw = philox4x32_10(i0, 3u, id.wlo, id.whi, id.k0, id.k1);
+                    if (mw_used == 1) mw = rare_block(i0, id);
                     const uint32_t word = mw_used == 0 ? m1 : (mw_used == 1 ? mw.x : mw.y);
                     ++mw_used;
                     cross = word < threshold(p, l, nl);
@@ -555,7 +565,7 @@ struct WalkerMixed {
         uint32_t passed = 0, refl = 0;
         uint32_t rawc = 0;  // entry of the voxel last passed into (its halo flags)
         int mw_used = 0;
-        uint4 mw = make_uint4(0, 0, 0, 0);
+        uint4 mw;  // words of substream 3, computed before the second membrane hit reads them
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
             if (k < nev) {
@@ -569,7 +579,7 @@ struct WalkerMixed {
                 bool cross = true;
                 if (nl != l) {
                     ++nhit;
-                    if (mw_used == 1) mw = philox4x32_10(i0, 3u, id.wlo, id.whi, id.k0, id.k1);
+                    if (mw_used == 1) mw = rare_block(i0, id);
                     const uint32_t word = mw_used == 0 ? m1 : (mw_used == 1 ? mw.x : mw.y);
                     ++mw_used;
                     cross = word < threshold(p, l, nl);
