@@ -20,10 +20,12 @@ namespace {
 
 using dev::Ids;
 
-// Five waves per SIMD: the double-precision walker then fits 96 registers
-// (a few bytes of spill outside the step) and runs about 7% faster than at
-// four; the mixed walker needs fewer registers and is not affected.
-#define RMS_WALK_OCCUPANCY __attribute__((amdgpu_waves_per_eu(5, 8)))
+// Waves per SIMD each walker asks for: five for the double-precision walker,
+// which then fits 96 registers (a few bytes of spill outside the step) and
+// runs about 7% faster than at four; six for the mixed walker, which keeps
+// it within 80 registers (left free, it grows past 85 with two waveform
+// shapes and drops to five waves, 16% slower).
+#define RMS_WALK_OCCUPANCY __attribute__((amdgpu_waves_per_eu(Walker::kWaves, 8)))
 
 // The angle table of the double-precision direction draw, copied to LDS by
 // the whole block before any thread leaves (one entry per thread).
