@@ -80,7 +80,7 @@ def _load():
     lib.rmso_run.argtypes = [C.c_void_p, C.c_int, i64_p, C.c_double, C.c_int, d_p, d_p, d_p,
                              u8_p, C.c_uint64, C.c_int64, i64_p, C.c_int64, C.c_double, C.c_int,
                              d_p, C.c_int, d_p, C.c_int, d_p, C.c_int, d_p, d_p, d_p, d_p, d_p,
-                             d_p, d_p, i64_p, d_p]
+                             d_p, d_p, i64_p, d_p, C.c_int, i64_p, d_p]
     lib.rmso_run.restype = C.c_int
     _lib = lib
     return lib
@@ -183,9 +183,12 @@ DUMP_FIELDS = ["dx", "dy", "dz", "R", "label", "ix", "iy", "iz", "ox", "oy", "oz
 
 
 def run(labels, voxel_um, D, kappa=None, T2=None, dead=None, *, seed, n_walkers, n_steps, dt,
-        waveform=None, dirs=None, bvals=None, walker_ids=None, n_threads=None, dump=False):
+        waveform=None, dirs=None, bvals=None, walker_ids=None, n_threads=None, dump=False,
+        rec_steps=None):
     """Run the oracle.  ``labels`` is a [nz, ny, nx] uint8/uint16 array (x
-    fastest in memory).  Returns a dict of numpy results."""
+    fastest in memory).  Returns a dict of numpy results.  ``rec_steps``
+    (ascending steps in 1..n_steps) adds ``records``: sum_alpha, m2, m4, D, K
+    after each of those steps (section 2.3, D(t) and K(t))."""
     lib = _load()
     lab = np.ascontiguousarray(labels)
     if lab.dtype not in (np.uint8, np.uint16):
@@ -218,6 +221,9 @@ def run(labels, voxel_um, D, kappa=None, T2=None, dead=None, *, seed, n_walkers,
     cnt = np.zeros(3, np.int64)
     K = 15 + 3 * ns
     wd = np.zeros((n_walkers, K)) if dump else None
+    rs = None if rec_steps is None else np.ascontiguousarray(rec_steps, np.int64)
+    nr = 0 if rs is None else rs.size
+    ro = np.zeros(max(nr, 1) * (22 + 2 * nd))
     if n_threads is None:
         n_threads = os.cpu_count() or 1
     rc = lib.rmso_run(lab.ctypes.data, lab.dtype.itemsize, _ptr(dims, C.c_int64), voxel_um, n,
@@ -228,7 +234,8 @@ def run(labels, voxel_um, D, kappa=None, T2=None, dead=None, *, seed, n_walkers,
                       _ptr(sig, C.c_double), _ptr(m2, C.c_double), _ptr(m4, C.c_double),
                       _ptr(Dd, C.c_double), _ptr(Kd, C.c_double), _ptr(sa, C.c_double),
                       _ptr(bd, C.c_double), _ptr(cnt, C.c_int64),
-                      None if wd is None else _ptr(wd, C.c_double))
+                      None if wd is None else _ptr(wd, C.c_double), nr, _ptr(rs, C.c_int64),
+                      _ptr(ro, C.c_double))
     if rc:
         raise OracleError(rc)
     out = dict(
@@ -239,4 +246,9 @@ def run(labels, voxel_um, D, kappa=None, T2=None, dead=None, *, seed, n_walkers,
     if wd is not None:
         out["dump"] = wd
         out["phase"] = wd[:, 15:].reshape(n_walkers, ns, 3)
+    if rs is not None:
+        R = ro[: nr * (22 + 2 * nd)].reshape(nr, 22 + 2 * nd)
+        out["records"] = dict(steps=rs.copy(), sum_alpha=R[:, 0].copy(), m2=R[:, 1:7].copy(),
+                              m4=R[:, 7:22].copy(), D=R[:, 22:22 + nd].copy(),
+                              K=R[:, 22 + nd:22 + 2 * nd].copy())
     return out

@@ -31,7 +31,9 @@
  *   - the phase is the right Riemann sum dt * sum_i g_i . (x_i - x_0) over the
  *     post-step positions, with the waveform scaled so that its discrete b
  *     value equals the requested one;
- *   - kurtosis uses moments weighted by alpha and divided by sum(alpha).
+ *   - kurtosis uses moments weighted by alpha and divided by sum(alpha);
+ *   - moments recorded at an earlier step t (D(t) and K(t), section 2.3) weight
+ *     each walker by alpha(t) = exp(-R(t)), the T2 integral up to that step.
  *
  * All arithmetic is IEEE double; build with -ffp-contract=off.
  */
@@ -371,6 +373,9 @@ typedef struct {
     int32_t* w_lab; /* [n][2] start, end label */
     int64_t* w_vox; /* [n][3] final voxel */
     double* w_off;  /* [n][3] final offset */
+    int n_rec;               /* record steps (ascending, 1..n_steps) */
+    const int64_t* rec_steps;
+    double* w_rec;           /* [n][n_rec][4] displacement (um) and R after each record step */
     atomic_llong next;
     atomic_int err;
 } run_ctx;
@@ -399,6 +404,7 @@ static void walk_one(run_ctx* c, int64_t slot) {
     double phi[3 * 8];
     memset(phi, 0, sizeof phi);
     uint32_t dirw[4];
+    int rec = 0; /* next record */
     for (int64_t i = 1; i <= c->n_steps; ++i) {
         const int64_t j = (i - 1) / 2;
         if (((i - 1) & 1) == 0) philox_block(c->seed, (uint32_t)j, 0u, wid, dirw);
@@ -415,6 +421,12 @@ static void walk_one(run_ctx* c, int64_t slot) {
         for (int s = 0; s < c->n_shapes; ++s) {
             const double G = c->waveform[(size_t)s * (size_t)c->n_steps + (size_t)(i - 1)];
             for (int a = 0; a < 3; ++a) phi[3 * s + a] += c->g.dt * G * w.dx[a];
+        }
+        if (rec < c->n_rec && c->rec_steps[rec] == i) {
+            double* o = c->w_rec + ((size_t)slot * (size_t)c->n_rec + (size_t)rec) * 4;
+            for (int a = 0; a < 3; ++a) o[a] = w.dx[a];
+            o[3] = w.R;
+            ++rec;
         }
     }
     for (int a = 0; a < 3; ++a) {
@@ -456,11 +468,16 @@ int rmso_run(const void* labels, int label_bytes, const int64_t dims[3], double 
              int64_t n_steps, double dt, int n_shapes, const double* waveform, int n_dirs,
              const double* dirs, int n_b, const double* bvals, int n_threads, double* signal,
              double* m2, double* m4, double* D_dir, double* K_dir, double* sum_alpha,
-             double* b_disc, int64_t counters[3], double* walker_dump) {
+             double* b_disc, int64_t counters[3], double* walker_dump, int n_rec,
+             const int64_t* rec_steps, double* rec_out) {
     if (!labels || (label_bytes != 1 && label_bytes != 2) || !dims || n_walkers < 0 ||
         n_steps < 0 || n_steps > 0xFFFFFFFFLL || n_shapes < 0 || n_shapes > 8 || n_dirs < 0 ||
-        n_b < 0 || (n_shapes > 0 && !waveform) || (n_dirs > 0 && !dirs))
+        n_b < 0 || (n_shapes > 0 && !waveform) || (n_dirs > 0 && !dirs) || n_rec < 0 ||
+        (n_rec > 0 && (!rec_steps || !rec_out)))
         return RMSO_E_INVALID_ARG;
+    for (int r = 0; r < n_rec; ++r)
+        if (rec_steps[r] < 1 || rec_steps[r] > n_steps || (r > 0 && rec_steps[r] <= rec_steps[r - 1]))
+            return RMSO_E_INVALID_ARG;
     const int64_t nvox = dims[0] * dims[1] * dims[2];
     if (dims[0] <= 0 || dims[1] <= 0 || dims[2] <= 0) return RMSO_E_INVALID_ARG;
     for (int64_t i = 0; i < nvox; ++i) {
@@ -515,7 +532,11 @@ int rmso_run(const void* labels, int label_bytes, const int64_t dims[3], double 
         c->w_lab = malloc(sizeof(int32_t) * 2 * n + 8);
         c->w_vox = malloc(sizeof(int64_t) * 3 * n + 8);
         c->w_off = malloc(sizeof(double) * 3 * n + 8);
-        if (!c->w_dx || !c->w_phi || !c->w_R || !c->w_cnt || !c->w_lab || !c->w_vox || !c->w_off)
+        c->n_rec = n_rec;
+        c->rec_steps = rec_steps;
+        c->w_rec = malloc(sizeof(double) * 4 * (size_t)n_rec * n + 8);
+        if (!c->w_dx || !c->w_phi || !c->w_R || !c->w_cnt || !c->w_lab || !c->w_vox || !c->w_off ||
+            !c->w_rec)
             rc = RMSO_E_OOM;
     }
     if (rc == RMSO_OK) {
@@ -602,6 +623,42 @@ int rmso_run(const void* labels, int label_bytes, const int64_t dims[3], double 
                 for (int s = 0; s < n_shapes; ++s) b_disc[s] = bd[s];
             if (counters)
                 for (int q = 0; q < 3; ++q) counters[q] = cnt[q];
+            /* recorded moments, the same sums at each record step t: rec_out
+             * per record holds sum alpha(t), M2[6], M4[15], D[n_dirs], K[n_dirs] */
+            for (int r = 0; r < n_rec; ++r) {
+                double* o = rec_out + (size_t)r * (22 + 2 * (size_t)n_dirs);
+                double ra = 0.0, r2[6] = {0}, r4[15] = {0};
+                for (int d = 0; d < n_dirs; ++d) p2[d] = p4[d] = 0.0;
+                for (size_t k = 0; k < n; ++k) {
+                    const double* x = c->w_rec + (k * (size_t)n_rec + (size_t)r) * 4;
+                    const double alpha = exp(-x[3]);
+                    ra += alpha;
+                    int q = 0;
+                    for (int a = 0; a < 3; ++a)
+                        for (int b = a; b < 3; ++b) r2[q++] += alpha * x[a] * x[b];
+                    q = 0;
+                    for (int a = 0; a < 3; ++a)
+                        for (int b = a; b < 3; ++b)
+                            for (int e = b; e < 3; ++e)
+                                for (int f = e; f < 3; ++f)
+                                    r4[q++] += alpha * x[a] * x[b] * x[e] * x[f];
+                    for (int d = 0; d < n_dirs; ++d) {
+                        const double pr =
+                            gh[3 * d] * x[0] + gh[3 * d + 1] * x[1] + gh[3 * d + 2] * x[2];
+                        p2[d] += alpha * pr * pr;
+                        p4[d] += alpha * pr * pr * pr * pr;
+                    }
+                }
+                const double tr = (double)rec_steps[r] * dt;
+                o[0] = ra;
+                for (int q = 0; q < 6; ++q) o[1 + q] = r2[q] / ra;
+                for (int q = 0; q < 15; ++q) o[7 + q] = r4[q] / ra;
+                for (int d = 0; d < n_dirs; ++d) {
+                    const double w2 = p2[d] / ra, w4 = p4[d] / ra;
+                    o[22 + d] = w2 / (2.0 * tr);
+                    o[22 + n_dirs + d] = w2 > 0.0 ? w4 / (w2 * w2) - 3.0 : 0.0;
+                }
+            }
             if (walker_dump) {
                 const size_t K = 15 + 3 * (size_t)n_shapes;
                 for (size_t k = 0; k < n; ++k) {
@@ -632,6 +689,7 @@ int rmso_run(const void* labels, int label_bytes, const int64_t dims[3], double 
         free(c->w_lab);
         free(c->w_vox);
         free(c->w_off);
+        free(c->w_rec);
         free(c);
     }
     free(allowed);
