@@ -283,6 +283,49 @@ def precision_report(args):
     print(json.dumps(line), flush=True)
 
 
+def record_report(args):
+    """Time dependence of D and K (section 2.3): the workload with its moments
+    recorded at ``--records`` equally spaced steps, against the same run without
+    records (the end results are identical; the recorded run walks one launch
+    per interval and reduces the moments at each record step)."""
+    import torch
+    import paper_2012_06478_amd as rms
+    assert torch.cuda.is_available(), "bench needs a GPU"
+    torch.cuda.set_device(0)
+    log(f"[records] building workload {args.workload}")
+    c = workload(args.workload)
+    prec = rms.RMS_FP64 if args.precision == "fp64" else rms.RMS_MIXED
+    sub = rms.rms_create_substrate(c["labels"], c["voxel_um"], c["D"], c["kappa"], c["T2"],
+                                   c.get("dead"))
+    n = c["n_steps"]
+    steps = np.unique(np.linspace(n / args.records, n, args.records).round().astype(np.int64))
+    run = dict(seed=c["seed"], n_walkers=c["n_walkers"], n_steps=n, dt=c["dt"],
+               waveform=c["waveform"], dirs=c["dirs"], bvals=c["bvals"], precision=prec)
+    rms.rms_run(sub, **run)  # warm-up of both paths
+    rms.rms_run_record(sub, record_steps=steps, **run)
+    plain = [rms.rms_run(sub, **run) for _ in range(args.steps)]
+    recd = [rms.rms_run_record(sub, record_steps=steps, **run) for _ in range(args.steps)]
+    sub.close()
+    ws = c["n_walkers"] * n
+    wall_p = min(r["wall_s"] for r in plain)
+    wall_r = min(r["wall_s"] for r in recd)
+    rr = recd[0]["records"]
+    line = {
+        "metric": "recorded walker-steps/s", "value": ws / wall_r, "unit": "walker-steps/s",
+        "higher_is_better": True, "data": "synthetic", "workload": c["name"],
+        "precision": args.precision, "n_records": int(steps.size),
+        "plain_walker_steps_per_s": ws / wall_p,
+        "kernel_ms_recorded": min(r["kernel_ms"] for r in recd),
+        "kernel_ms_plain": min(r["kernel_ms"] for r in plain),
+        "end_results_identical": bool(np.array_equal(recd[0]["signal"], plain[0]["signal"])
+                                      and np.array_equal(recd[0]["m2"], plain[0]["m2"])),
+        "t_ms": [float(x) for x in steps[:: max(1, steps.size // 10)] * c["dt"]],
+        "D_dir0": [float(x) for x in rr["D"][:: max(1, steps.size // 10), 0]],
+        "K_dir0": [float(x) for x in rr["K"][:: max(1, steps.size // 10), 0]],
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -300,6 +343,9 @@ def main():
     ap.add_argument("--serve-load", type=float, default=0.7)
     ap.add_argument("--serve-check", type=int, default=8,
                     help="requests re-run in fp64 to report the served signal error")
+    ap.add_argument("--records", type=int, default=0,
+                    help="time series of D and K: record the moments at this many steps and "
+                         "report the recorded run's throughput against the plain one")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run only a plain 1 GiB device copy (3 times), to scale the "
                          "FETCH_SIZE/WRITE_SIZE counters")
@@ -311,6 +357,9 @@ def main():
 
     if args.precision_report:
         precision_report(args)
+        return
+    if args.records > 0:
+        record_report(args)
         return
     if args.serve:
         if args.precision == "fp64" and "--precision" not in sys.argv:

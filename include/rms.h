@@ -175,6 +175,45 @@ int rms_run(const rms_substrate* sub, const rms_params* params, uint64_t seed, i
             const double* dirs, int n_b, const double* bvals, int precision, void* hip_stream,
             rms_result* out);
 
+/* Displacement moments recorded during a walk: the time dependence of D and
+ * K (section 2.3 defines both from the moments of the displacement over the
+ * diffusion time t).  After step steps[r] (t = steps[r] dt) each walker is
+ * weighted by alpha(t) = exp(-R(t)), R(t) its T2 integral up to that step
+ * (section 2.1.4, Eq. wt-relax), and
+ *   sum_alpha  [n_rec]           sum over walkers of alpha(t)
+ *   m2         [n_rec][6]        alpha(t)-weighted <dx_i dx_j> / sum_alpha
+ *   m4         [n_rec][15]       alpha(t)-weighted <dx_i dx_j dx_k dx_l> / sum_alpha
+ *   D_dir      [n_rec][n_dirs]   (g.M2.g) / (2 t), or NULL
+ *   K_dir      [n_rec][n_dirs]   (M4:g^4) / (g.M2.g)^2 - 3, or NULL
+ * with the component orders of rms_result.  n_rec is 1..RMS_MAX_RECORDS and
+ * steps ascend strictly within 1..n_steps.  The caller allocates every array;
+ * sum_alpha, m2 and m4 are required. */
+#define RMS_MAX_RECORDS 4096
+typedef struct {
+    int n_rec;
+    const int64_t* steps;
+    double* sum_alpha;
+    double* m2;
+    double* m4;
+    double* D_dir;
+    double* K_dir;
+} rms_record;
+
+/* rms_run with the displacement moments recorded at rec->steps.  Every other
+ * argument and every field of `out` is as for rms_run, and the end results
+ * equal rms_run's bit for bit (a walker's trajectory depends only on seed,
+ * walker and step).  The walk runs as one launch per interval between record
+ * steps, keeping the walker states in device memory (120 extra bytes per
+ * walker in FP64, 100 in the mixed form, with one waveform shape);
+ * out->kernel_ms covers the walk launches and the record reductions between
+ * them.  Errors as rms_run, and RMS_E_INVALID_ARG for a malformed record
+ * list. */
+int rms_run_record(const rms_substrate* sub, const rms_params* params, uint64_t seed,
+                   int64_t n_walkers, int64_t n_steps, double dt_ms, int n_shapes,
+                   const double* waveform, int n_dirs, const double* dirs, int n_b,
+                   const double* bvals, int precision, void* hip_stream, const rms_record* rec,
+                   rms_result* out);
+
 /* ---------------------------------------------------------------------------
  * Serving: continuous batching of simulation requests on one GPU.
  *

@@ -47,6 +47,13 @@ class _Params(C.Structure):
                 ("kappa", C.POINTER(C.c_double)), ("T2", C.POINTER(C.c_double))]
 
 
+class _Record(C.Structure):
+    _fields_ = [("n_rec", C.c_int), ("steps", C.POINTER(C.c_int64)),
+                ("sum_alpha", C.POINTER(C.c_double)), ("m2", C.POINTER(C.c_double)),
+                ("m4", C.POINTER(C.c_double)), ("D_dir", C.POINTER(C.c_double)),
+                ("K_dir", C.POINTER(C.c_double))]
+
+
 class _Result(C.Structure):
     _fields_ = [("signal", C.POINTER(C.c_double)), ("m2", C.c_double * 6),
                 ("m4", C.c_double * 15), ("D_dir", C.POINTER(C.c_double)),
@@ -100,6 +107,10 @@ def _load():
                             C.c_double, C.c_int, dp, C.c_int, dp, C.c_int, dp, C.c_int,
                             C.c_void_p, C.POINTER(_Result)]
     lib.rms_run.restype = C.c_int
+    lib.rms_run_record.argtypes = [C.c_void_p, C.POINTER(_Params), C.c_uint64, C.c_int64,
+                                   C.c_int64, C.c_double, C.c_int, dp, C.c_int, dp, C.c_int, dp,
+                                   C.c_int, C.c_void_p, C.POINTER(_Record), C.POINTER(_Result)]
+    lib.rms_run_record.restype = C.c_int
     lib.rms_server_create.argtypes = [C.c_size_t, C.c_int, C.POINTER(C.c_void_p)]
     lib.rms_server_create.restype = C.c_int
     lib.rms_server_submit.argtypes = [C.c_void_p, C.POINTER(_Request), C.POINTER(C.c_int64)]
@@ -120,7 +131,8 @@ def exported_symbols() -> list[str]:
     """Names the library exports through the C ABI (for load checks)."""
     lib = _load()
     names = ["rms_abi_version", "rms_last_error", "rms_create_substrate",
-             "rms_destroy_substrate", "rms_run", "rms_server_create", "rms_server_submit",
+             "rms_destroy_substrate", "rms_run", "rms_run_record", "rms_server_create",
+             "rms_server_submit",
              "rms_server_poll", "rms_server_wait", "rms_server_stats_get", "rms_server_destroy"]
     return [n for n in names if hasattr(lib, n)]
 
@@ -273,6 +285,40 @@ def rms_run(sub: Substrate, *, seed, n_walkers, n_steps, dt, waveform=None, dirs
     return out
 
 
+def rms_run_record(sub: Substrate, *, seed, n_walkers, n_steps, dt, record_steps,
+                   waveform=None, dirs=None, bvals=None, precision=RMS_FP64, params=None,
+                   stream=None, dump=False) -> dict:
+    """``rms_run`` plus the displacement moments after each of ``record_steps``
+    (ascending, 1..n_steps): the result gains ``records`` with ``steps``,
+    ``sum_alpha`` [n_rec], ``m2`` [n_rec, 6], ``m4`` [n_rec, 15], ``D`` and
+    ``K`` [n_rec, n_dirs] (see ``rms_run_record`` in ``include/rms.h``)."""
+    lib = _load()
+    W, g, b = _protocol(n_steps, waveform, dirs, bvals)
+    keep = []
+    pp = _params(params, keep)
+    rb = _ResultBuffers(W.shape[0], b.size, g.shape[0])
+    wd = np.zeros((int(n_walkers), RMS_DUMP_FIXED + 3 * W.shape[0])) if dump else None
+    rb.res.walker_dump = _dptr(wd) if wd is not None else None
+    steps = np.ascontiguousarray(record_steps, np.int64).reshape(-1)
+    nr, nd = steps.size, g.shape[0]
+    sa, m2, m4 = np.zeros(max(nr, 1)), np.zeros((max(nr, 1), 6)), np.zeros((max(nr, 1), 15))
+    Dd, Kd = np.zeros((max(nr, 1), max(nd, 1))), np.zeros((max(nr, 1), max(nd, 1)))
+    rec = _Record(nr, steps.ctypes.data_as(C.POINTER(C.c_int64)), _dptr(sa), _dptr(m2),
+                  _dptr(m4), _dptr(Dd), _dptr(Kd))
+    rc = lib.rms_run_record(sub.handle, None if pp is None else C.byref(pp),
+                            int(seed) & (2**64 - 1), int(n_walkers), int(n_steps), float(dt),
+                            W.shape[0], _dptr(W), nd, _dptr(g), b.size, _dptr(b),
+                            int(precision), _stream_handle(stream), C.byref(rec), C.byref(rb.res))
+    _check(rc)
+    out = rb.to_dict()
+    out["records"] = dict(steps=steps.copy(), sum_alpha=sa[:nr].copy(), m2=m2[:nr].copy(),
+                          m4=m4[:nr].copy(), D=Dd[:nr, :nd].copy(), K=Kd[:nr, :nd].copy())
+    if wd is not None:
+        out["dump"] = wd
+        out["phase"] = wd[:, RMS_DUMP_FIXED:].reshape(int(n_walkers), W.shape[0], 3)
+    return out
+
+
 # ------------------------------------------------------------------ server --
 
 def rms_server_create(mem_budget_bytes: int = 0, slice_steps: int = 0):
@@ -319,6 +365,6 @@ def rms_server_destroy(srv) -> None:
 
 
 __all__ = ["rms_abi_version", "rms_last_error", "rms_create_substrate", "rms_destroy_substrate",
-           "rms_run", "rms_server_create", "rms_server_submit", "rms_server_poll",
+           "rms_run", "rms_run_record", "rms_server_create", "rms_server_submit", "rms_server_poll",
            "rms_server_wait", "rms_server_stats_get", "rms_server_destroy", "Substrate", "RmsError", "RMS_FP64", "RMS_MIXED", "exported_symbols",
            "DUMP_FIELDS"]

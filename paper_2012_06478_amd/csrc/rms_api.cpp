@@ -583,4 +583,133 @@ int rms_run(const rms_substrate* sub, const rms_params* params, uint64_t seed, i
     return RMS_OK;
 }
 
+int rms_run_record(const rms_substrate* sub, const rms_params* params, uint64_t seed,
+                   int64_t n_walkers, int64_t n_steps, double dt_ms, int n_shapes,
+                   const double* waveform, int n_dirs, const double* dirs, int n_b,
+                   const double* bvals, int precision, void* hip_stream, const rms_record* rec,
+                   rms_result* out) {
+    using rms::fail;
+    const auto t0 = std::chrono::steady_clock::now();
+    rms::clear_error();
+    if (!out) return fail(RMS_E_INVALID_ARG, "result is required");
+    if (!rec) return fail(RMS_E_INVALID_ARG, "record list is required");
+    if (rec->n_rec < 1 || rec->n_rec > RMS_MAX_RECORDS)
+        return fail(RMS_E_INVALID_ARG, "n_rec must be in 1..RMS_MAX_RECORDS");
+    if (!rec->steps || !rec->sum_alpha || !rec->m2 || !rec->m4)
+        return fail(RMS_E_INVALID_ARG, "record steps, sum_alpha, m2 and m4 are required");
+    rms::RunSetup r;
+    int rc = rms::prepare_run(sub, params, seed, n_walkers, n_steps, dt_ms, n_shapes, waveform,
+                              n_dirs, dirs, n_b, bvals, precision, r);
+    if (rc) return rc;
+    const int n_rec = rec->n_rec;
+    for (int k = 0; k < n_rec; ++k)
+        if (rec->steps[k] < 1 || rec->steps[k] > n_steps ||
+            (k > 0 && rec->steps[k] <= rec->steps[k - 1]))
+            return fail(RMS_E_INVALID_ARG, "record steps must ascend strictly within 1..n_steps");
+
+    int prev_dev = 0;
+    RMS_HIP(hipGetDevice(&prev_dev));
+    struct DeviceGuard {
+        int prev;
+        ~DeviceGuard() { hipSetDevice(prev); }
+    } guard{prev_dev};
+    RMS_HIP(hipSetDevice(sub->device));
+
+    hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+    rms::DeviceRun dr;
+    rc = dr.create(*sub, r, true, stream);
+    if (rc) return rc;
+
+    // the walk plan, one packed item per block of thread slots (their step
+    // range is set on the device before each interval) and the reduced values
+    // of each record (the layout of ReducePlan::result without signals)
+    const int64_t n_items64 = (dr.wp.n_slots + rms::kBlock - 1) / rms::kBlock;
+    if (n_items64 > INT32_MAX) return fail(RMS_E_INVALID_ARG, "too many walkers");
+    const int n_items = static_cast<int>(n_items64);
+    const int rec_stride = rms::kAccFixed + 2 * n_dirs;
+    const size_t o_items = (sizeof(rms::WalkPlan) + 255) / 256 * 256;
+    const size_t o_rec = o_items + (static_cast<size_t>(n_items) * sizeof(rms::PackedItem) + 255) /
+                                       256 * 256;
+    const size_t extra = o_rec + static_cast<size_t>(n_rec) * rec_stride * sizeof(double);
+    void* xb = nullptr;
+    RMS_HIP(hipMallocAsync(&xb, extra, stream));
+    dr.ptrs.push_back(xb);
+    auto* d_plan = static_cast<rms::WalkPlan*>(xb);
+    auto* d_items = reinterpret_cast<rms::PackedItem*>(static_cast<uint8_t*>(xb) + o_items);
+    auto* d_rec = reinterpret_cast<double*>(static_cast<uint8_t*>(xb) + o_rec);
+    std::vector<rms::PackedItem> items(static_cast<size_t>(n_items));
+    for (int i = 0; i < n_items; ++i)
+        items[i] = rms::PackedItem{static_cast<int64_t>(i) * rms::kBlock, 0, 0u, 0u, 0u};
+    RMS_HIP(hipMemcpyAsync(d_plan, &dr.wp, sizeof(rms::WalkPlan), hipMemcpyHostToDevice, stream));
+    RMS_HIP(hipMemcpyAsync(d_items, items.data(), items.size() * sizeof(rms::PackedItem),
+                           hipMemcpyHostToDevice, stream));
+
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    struct EventGuard {
+        hipEvent_t* a;
+        hipEvent_t* b;
+        ~EventGuard() {
+            if (*a) hipEventDestroy(*a);
+            if (*b) hipEventDestroy(*b);
+        }
+    } eguard{&ev0, &ev1};
+    RMS_HIP(hipEventCreate(&ev0));
+    RMS_HIP(hipEventCreate(&ev1));
+    RMS_HIP(rms::launch_order(dr.wp, stream));
+    RMS_HIP(hipEventRecord(ev0, stream));
+    const auto record = [&](int k) {
+        rms::ReducePlan rr = dr.rp;
+        rr.n_shapes = 0;
+        rr.n_sig = 0;
+        rr.n_acc = rms::kAccFixed;
+        rr.t_ms = static_cast<double>(rec->steps[k]) * r.dt;
+        rr.result = d_rec + static_cast<size_t>(k) * rec_stride;
+        return rms::launch_reduce(rr, stream);
+    };
+    int64_t b = 0;
+    for (int k = 0; k <= n_rec; ++k) {
+        const int64_t e = k < n_rec ? rec->steps[k] : n_steps;
+        if (e > b) {  // one launch per interval; an intermediate end writes the records
+            RMS_HIP(rms::launch_item_range(d_items, n_items, static_cast<uint32_t>(b),
+                                           static_cast<uint32_t>(e),
+                                           e < n_steps ? rms::kItemRecord : 0u, stream));
+            RMS_HIP(rms::launch_walk_packed(d_items, n_items, d_plan, precision,
+                                            sub->dev_label_bytes, r.n_shapes, stream));
+            b = e;
+        }
+        if (k < n_rec) RMS_HIP(record(k));
+    }
+    RMS_HIP(hipEventRecord(ev1, stream));
+    RMS_HIP(rms::launch_reduce(dr.rp, stream));
+
+    std::vector<double> res(r.n_res), recv(static_cast<size_t>(n_rec) * rec_stride);
+    RMS_HIP(hipMemcpyAsync(res.data(), dr.rp.result, r.n_res * sizeof(double),
+                           hipMemcpyDeviceToHost, stream));
+    RMS_HIP(hipMemcpyAsync(recv.data(), d_rec, recv.size() * sizeof(double),
+                           hipMemcpyDeviceToHost, stream));
+    if (out->walker_dump)
+        RMS_HIP(hipMemcpyAsync(out->walker_dump, dr.wp.wstate,
+                               static_cast<size_t>(n_walkers) * r.width * sizeof(double),
+                               hipMemcpyDeviceToHost, stream));
+    RMS_HIP(hipStreamSynchronize(stream));
+    float ms = 0.0f;
+    RMS_HIP(hipEventElapsedTime(&ms, ev0, ev1));
+    rms::fill_result(r, res.data(), out);
+    for (int k = 0; k < n_rec; ++k) {
+        const double* v = recv.data() + static_cast<size_t>(k) * rec_stride;
+        rec->sum_alpha[k] = v[0];
+        for (int q = 0; q < 6; ++q) rec->m2[6 * k + q] = v[1 + q];
+        for (int q = 0; q < 15; ++q) rec->m4[15 * k + q] = v[7 + q];
+        for (int d = 0; d < n_dirs; ++d) {
+            if (rec->D_dir) rec->D_dir[static_cast<size_t>(k) * n_dirs + d] = v[rms::kAccFixed + d];
+            if (rec->K_dir)
+                rec->K_dir[static_cast<size_t>(k) * n_dirs + d] = v[rms::kAccFixed + n_dirs + d];
+        }
+    }
+    out->kernel_ms = ms;
+    out->queue_s = 0.0;
+    out->wall_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    return RMS_OK;
+}
+
 }  // extern "C"

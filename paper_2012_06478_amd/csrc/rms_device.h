@@ -666,18 +666,23 @@ struct WalkerMixed {
     }
 };
 
-// Steps [b, e) of one walker, b a multiple of 4 (every caller starts a range
-// at step 0, at a segment of a multiple of 4 steps or at a server slice of a
-// multiple of 4 steps): direction words two steps per Philox block, first
-// membrane words four steps per block, both blocks computed under
-// wave-uniform branches at the step that opens them.  One step per iteration
-// keeps consecutive steps from being interleaved by the scheduler, which
-// would raise register use.
-template <class Walker, typename LabelT>
+// Steps [b, e) of one walker: direction words two steps per Philox block,
+// first membrane words four steps per block, both blocks computed under
+// wave-uniform branches at the step that opens them.  With kAnyStart false, b
+// is a multiple of 4 (step 0, a segment of the persistent walk or a server
+// slice); with kAnyStart true (a walk resumed after a record step) a range
+// that starts inside a block first computes the blocks its first steps read.
+// One step per iteration keeps consecutive steps from being interleaved by the
+// scheduler, which would raise register use.
+template <bool kAnyStart = false, class Walker, typename LabelT>
 __device__ __forceinline__ void walk_range(const WalkPlan& p, const LabelT* __restrict__ lab,
                                            Walker& W, uint32_t b, uint32_t e, const Ids& id,
                                            const double* trig) {
     uint4 wd = make_uint4(0, 0, 0, 0), wm = make_uint4(0, 0, 0, 0);
+    if constexpr (kAnyStart) {
+        if (b & 1u) wd = philox4x32_10(b >> 1, 0u, id.wlo, id.whi, id.k0, id.k1);
+        if (b & 3u) wm = philox4x32_10(b >> 2, 1u, id.wlo, id.whi, id.k0, id.k1);
+    }
     for (uint32_t i0 = b; i0 < e; ++i0) {
         const bool odd = (i0 & 1u) != 0;
         if (!odd) wd = philox4x32_10(i0 >> 1, 0u, id.wlo, id.whi, id.k0, id.k1);

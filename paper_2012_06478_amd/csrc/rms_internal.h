@@ -70,13 +70,15 @@ constexpr int kSegCtlFixed = kSegQueues + 1;
 
 // One block of a packed launch: thread slots [first_slot, first_slot + kBlock)
 // of plan `plan` (walker = slot, or plan.order[slot]), steps [step_begin,
-// step_end).
+// step_end) from any step_begin.  flags: kItemRecord also writes each
+// walker's record (plan.wstate) when the range stops before the last step.
 struct PackedItem {
     int64_t first_slot;
     int plan;
     uint32_t step_begin, step_end;
-    uint32_t pad;
+    uint32_t flags;
 };
+constexpr uint32_t kItemRecord = 1u;
 
 // Everything the reduction kernels read.
 struct ReducePlan {
@@ -104,9 +106,13 @@ hipError_t launch_walk(const WalkPlan& p, int precision, hipStream_t s);
 // A packed launch over several runs that share precision, label width and
 // shape count: each block advances its walkers by a range of steps, starting
 // from the stored state (or the start when step_begin == 0) and storing the
-// state again (or the final record when step_end == n_steps).
+// state again (or the final record when step_end == n_steps; with kItemRecord
+// the record as well).
 hipError_t launch_walk_packed(const PackedItem* items, int n_items, const WalkPlan* plans,
                               int precision, int label_bytes, int n_shapes, hipStream_t s);
+// Sets the step range and flags of items[0, n_items) on the device.
+hipError_t launch_item_range(PackedItem* items, int n_items, uint32_t step_begin,
+                             uint32_t step_end, uint32_t flags, hipStream_t s);
 // Walker order for one run (rms_walk.hip): slots in blocks that run on one
 // XCD take walkers whose start voxels are close.  order_bytes() is the device
 // memory it needs (0 when the run keeps slot i = walker i), order_slots() the

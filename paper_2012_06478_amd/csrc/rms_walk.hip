@@ -86,11 +86,26 @@ __global__ __launch_bounds__(kBlock) RMS_WALK_OCCUPANCY void walk_packed_kernel(
     Walker W;
     if (it.step_begin == 0) W.init(p, lab, id);
     else W = *st;
-    dev::walk_range(p, lab, W, it.step_begin, it.step_end, id, trig);
-    if (it.step_end == static_cast<uint32_t>(p.n_steps))
+    dev::walk_range<true>(p, lab, W, it.step_begin, it.step_end, id, trig);
+    if (it.step_end == static_cast<uint32_t>(p.n_steps)) {
         W.finish(p, p.wstate + w * (kDumpFixed + 3 * p.n_shapes));
-    else
+    } else {
         *st = W;
+        if (it.flags & kItemRecord) W.finish(p, p.wstate + w * (kDumpFixed + 3 * p.n_shapes));
+    }
+}
+
+// Step range and flags of every item of a packed launch (a run recorded at
+// several steps walks one interval per launch over the same items).
+__global__ __launch_bounds__(kBlock) void item_range_kernel(PackedItem* items, int n,
+                                                            uint32_t b, uint32_t e,
+                                                            uint32_t flags) {
+    const int i = static_cast<int>(blockIdx.x) * kBlock + static_cast<int>(threadIdx.x);
+    if (i < n) {
+        items[i].step_begin = b;
+        items[i].step_end = e;
+        items[i].flags = flags;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -456,6 +471,14 @@ hipError_t launch_walk(const WalkPlan& p, int precision, hipStream_t s) {
     if (precision == RMS_FP64)
         return u8 ? run_ns<dev::WalkerF64, uint8_t>(p, s) : run_ns<dev::WalkerF64, uint16_t>(p, s);
     return u8 ? run_ns<dev::WalkerMixed, uint8_t>(p, s) : run_ns<dev::WalkerMixed, uint16_t>(p, s);
+}
+
+hipError_t launch_item_range(PackedItem* items, int n_items, uint32_t step_begin,
+                             uint32_t step_end, uint32_t flags, hipStream_t s) {
+    if (n_items <= 0) return hipSuccess;
+    item_range_kernel<<<dim3(static_cast<unsigned>((n_items + kBlock - 1) / kBlock)), kBlock, 0,
+                        s>>>(items, n_items, step_begin, step_end, flags);
+    return hipGetLastError();
 }
 
 hipError_t launch_walk_packed(const PackedItem* items, int n_items, const WalkPlan* plans,
