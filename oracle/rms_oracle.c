@@ -23,6 +23,9 @@
  *                    two or three membranes met in one step) use words 0 and 1
  *                    of block i-1;
  *       substream 2: the walker's start, blocks 0 and 1;
+ *       substream 4: the saturation decisions at absorbing membranes of step i
+ *                    (first to third membrane met) use words 0 to 2 of block
+ *                    i-1;
  *   - a word w maps to the uniform deviate (w + 1/2) 2^-32, exact in FP64;
  *   - the volume is periodic; displacements are unwrapped;
  *   - after a permeation into a compartment of different diffusivity the
@@ -33,7 +36,12 @@
  *     value equals the requested one;
  *   - kurtosis uses moments weighted by alpha and divided by sum(alpha);
  *   - moments recorded at an earlier step t (D(t) and K(t), section 2.3) weight
- *     each walker by alpha(t) = exp(-R(t)), the T2 integral up to that step.
+ *     each walker by alpha(t) = exp(-R(t)), the T2 integral up to that step;
+ *   - an absorbing membrane (magnetization transfer, end of section 2.1.3)
+ *     saturates a walker that meets it with probability P_MT, decided before
+ *     and independently of the permeation decision at the same face; the
+ *     saturated walker keeps walking with weight 0 (Eq. wt-mt), held as
+ *     R = infinity so that alpha = exp(-R) = 0.
  *
  * All arithmetic is IEEE double; build with -ffp-contract=off.
  */
@@ -126,6 +134,35 @@ double rmso_perm_prob(double kappa, double D1, double D2, double dt) {
     return P > 1.0 ? 1.0 : P;
 }
 
+/* Saturation probability at an absorbing membrane (end of section 2.1.3):
+ * P_MT = rho ds C_3 / D0 with rho the surface relaxivity, ds and D0 of the
+ * walker's compartment and C_3 = 2/3 as in Eq. (perm-prob).  Clamped to 1. */
+double rmso_mt_prob(double rho, double D, double dt) {
+    if (rho <= 0.0) return 0.0;
+    const double C3 = 2.0 / 3.0;
+    const double P = rho * rmso_step_size(D, dt) / D * C3;
+    return P > 1.0 ? 1.0 : P;
+}
+
+/* Saturation thresholds for a walker in label a meeting a face to label b,
+ * rho[a * n_labels + b] (a saturation word w < T saturates; T = floor(P 2^32);
+ * 0 on equal labels, which are no membrane). */
+int rmso_mt_tables(int n_labels, const double* D, const double* rho, const uint8_t* dead,
+                   double dt, uint64_t* thresh_mt) {
+    if (n_labels <= 0 || !rho || !(dt > 0.0)) return RMSO_E_INVALID_ARG;
+    for (int a = 0; a < n_labels; ++a)
+        for (int b = 0; b < n_labels; ++b) {
+            const double r = rho[a * n_labels + b];
+            if (!(r >= 0.0) || isinf(r)) return RMSO_E_INVALID_ARG;
+            double P = 0.0;
+            if (a != b && !(dead && dead[a])) P = rmso_mt_prob(r, D[a], dt);
+            double t = floor(P * 4294967296.0);
+            if (t > 4294967296.0) t = 4294967296.0;
+            thresh_mt[a * n_labels + b] = (uint64_t)t;
+        }
+    return RMSO_OK;
+}
+
 /* Tables for one run: step length per label in voxel units, the 33-bit
  * permeation thresholds (a membrane word w < T permeates; T = floor(P 2^32)),
  * and 1/T2 per label (T2 = inf gives 0), section 2.1.4 Eq. (wt-relax).
@@ -201,6 +238,7 @@ typedef struct {
     const double* sigma;
     const uint64_t* thresh;
     const double* inv_T2;
+    const uint64_t* thresh_mt; /* saturation thresholds, or NULL: no absorbing membranes */
 } rmso_geom;
 
 typedef struct {
@@ -223,7 +261,8 @@ static double clamp01(double x) { return x < 0.0 ? 0.0 : (x > 1.0 ? 1.0 : x); }
 /* One step of one walker (section 2.2, items 2-4; section 2.1.1 and the
  * corner-reflector figure; section 2.1.2-2.1.3).  v is the unit direction,
  * mw are the step's membrane words (the caller supplies them lazily through
- * get_mw).  The walker travels along v; each time the remaining path reaches
+ * get_mw: index k < 3 is the permeation word of the k-th membrane met, 16 + k
+ * its saturation word).  The walker travels along v; each time the remaining path reaches
  * a voxel face it either passes (same label on the other side), permeates
  * with probability P (different label), or is reflected specularly
  * (component normal to the face flips).  Returns the number of face events or
@@ -281,6 +320,10 @@ static int walk_step(const rmso_geom* g, rmso_walker* w, const double v_in[3], m
             cross = 1;
         } else {
             ++w->n_hit;
+            if (g->thresh_mt) {
+                const uint64_t tm = g->thresh_mt[w->label * g->n_labels + nl];
+                if (tm > 0 && (uint64_t)get_mw(mw_ctx, 16 + mw_used) < tm) w->R = INFINITY;
+            }
             const uint32_t m = get_mw(mw_ctx, mw_used++);
             cross = (uint64_t)m < g->thresh[w->label * g->n_labels + nl];
             if (cross) ++w->n_perm;
@@ -307,6 +350,10 @@ typedef struct {
 static uint32_t philox_mw(void* p, int k) {
     const philox_mw_ctx* c = (const philox_mw_ctx*)p;
     uint32_t w[4];
+    if (k >= 16) {
+        philox_block(c->seed, c->index, 4u, c->walker, w);
+        return w[k - 16];
+    }
     if (k == 0) {
         philox_block(c->seed, c->index / 4u, 1u, c->walker, w);
         return w[c->index % 4u];
@@ -469,7 +516,7 @@ int rmso_run(const void* labels, int label_bytes, const int64_t dims[3], double 
              const double* dirs, int n_b, const double* bvals, int n_threads, double* signal,
              double* m2, double* m4, double* D_dir, double* K_dir, double* sum_alpha,
              double* b_disc, int64_t counters[3], double* walker_dump, int n_rec,
-             const int64_t* rec_steps, double* rec_out) {
+             const int64_t* rec_steps, double* rec_out, const double* rho) {
     if (!labels || (label_bytes != 1 && label_bytes != 2) || !dims || n_walkers < 0 ||
         n_steps < 0 || n_steps > 0xFFFFFFFFLL || n_shapes < 0 || n_shapes > 8 || n_dirs < 0 ||
         n_b < 0 || (n_shapes > 0 && !waveform) || (n_dirs > 0 && !dirs) || n_rec < 0 ||
@@ -492,6 +539,11 @@ int rmso_run(const void* labels, int label_bytes, const int64_t dims[3], double 
     int rc = (sigma && inv_T2 && thresh && kscale && bd) ? RMSO_OK : RMSO_E_OOM;
     if (rc == RMSO_OK)
         rc = rmso_tables(n_labels, D, kappa, T2, dead, dt, voxel_um, sigma, thresh, inv_T2);
+    uint64_t* thresh_mt = NULL;
+    if (rc == RMSO_OK && rho) {
+        thresh_mt = malloc(sizeof(uint64_t) * (size_t)n_labels * n_labels);
+        rc = thresh_mt ? rmso_mt_tables(n_labels, D, rho, dead, dt, thresh_mt) : RMSO_E_OOM;
+    }
     if (rc == RMSO_OK) rc = rmso_bscale(n_shapes, n_steps, dt, waveform, n_b, bvals, bd, kscale);
 
     int64_t* allowed = NULL;
@@ -516,7 +568,7 @@ int rmso_run(const void* labels, int label_bytes, const int64_t dims[3], double 
     const size_t n = (size_t)n_walkers;
     if (rc == RMSO_OK) {
         c->g = (rmso_geom){labels, label_bytes, {dims[0], dims[1], dims[2]}, n_labels, voxel_um,
-                           dt, sigma, thresh, inv_T2};
+                           dt, sigma, thresh, inv_T2, thresh_mt};
         c->seed = seed;
         c->n_walkers = n_walkers;
         c->walker_ids = walker_ids;
@@ -696,6 +748,7 @@ int rmso_run(const void* labels, int label_bytes, const int64_t dims[3], double 
     free(sigma);
     free(inv_T2);
     free(thresh);
+    free(thresh_mt);
     free(kscale);
     free(bd);
     return rc;
