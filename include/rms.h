@@ -26,7 +26,7 @@
 extern "C" {
 #endif
 
-#define RMS_ABI_VERSION 1
+#define RMS_ABI_VERSION 2
 
 /* Error codes. */
 #define RMS_OK 0
@@ -82,12 +82,24 @@ typedef struct rms_substrate rms_substrate;
  *          perm-prob-general);
  *   T2     [n_labels] transverse relaxation time per label (ms), > 0,
  *          INFINITY for none; NULL means no relaxation (section 2.1.4, Eq.
- *          wt-relax). */
+ *          wt-relax);
+ *   rho    [n_labels * n_labels] surface relaxivity (um/ms), >= 0, row-major:
+ *          rho[a * n_labels + b] makes the faces from label a to label b
+ *          absorbing for walkers in a (magnetization transfer, end of section
+ *          2.1.3): such a walker is saturated with probability
+ *          P_MT = rho ds_a C_3 / D_a (at most RMS_MAX_PERM_PROB, else
+ *          RMS_E_PROB_TOO_LARGE), decided at the membrane before and
+ *          independently of the permeation decision, and keeps walking with
+ *          weight 0 (Eq. wt-mt; its R becomes INFINITY in walker_dump).  NULL
+ *          or all zero: no membrane absorbs.  A run with absorbing membranes
+ *          walks in one launch (not the persistent walk).  If every walker is
+ *          saturated, sum_alpha is 0 and the normalized results are NaN. */
 typedef struct {
     int n_labels;
     const double* D;
     const double* kappa;
     const double* T2;
+    const double* rho;
 } rms_params;
 
 /* Results of one run.  The caller allocates every array it wants filled and

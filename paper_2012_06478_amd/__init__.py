@@ -44,7 +44,8 @@ class RmsError(RuntimeError):
 
 class _Params(C.Structure):
     _fields_ = [("n_labels", C.c_int), ("D", C.POINTER(C.c_double)),
-                ("kappa", C.POINTER(C.c_double)), ("T2", C.POINTER(C.c_double))]
+                ("kappa", C.POINTER(C.c_double)), ("T2", C.POINTER(C.c_double)),
+                ("rho", C.POINTER(C.c_double))]
 
 
 class _Record(C.Structure):
@@ -227,8 +228,10 @@ def _params(params, keep):
     kap = None if kap is None else np.ascontiguousarray(kap, np.float64).reshape(-1)
     t2 = params.get("T2")
     t2 = None if t2 is None else np.ascontiguousarray(t2, np.float64)
-    keep += [Dv, kap, t2]
-    return _Params(Dv.size, _dptr(Dv), _dptr(kap), _dptr(t2))
+    rho = params.get("rho")
+    rho = None if rho is None else np.ascontiguousarray(rho, np.float64).reshape(-1)
+    keep += [Dv, kap, t2, rho]
+    return _Params(Dv.size, _dptr(Dv), _dptr(kap), _dptr(t2), _dptr(rho))
 
 
 class _ResultBuffers:
@@ -264,7 +267,8 @@ def rms_run(sub: Substrate, *, seed, n_walkers, n_steps, dt, waveform=None, dirs
     """Run the walk; returns a dict of numpy results (see ``include/rms.h``).
 
     ``params``: optional dict with ``D``, ``kappa``, ``T2`` overriding the
-    substrate's tissue parameters.  ``stream``: a torch.cuda.Stream or a raw
+    substrate's tissue parameters, and ``rho`` [n, n] making membranes
+    absorbing (magnetization transfer).  ``stream``: a torch.cuda.Stream or a raw
     hipStream_t (int); None runs on the null stream."""
     lib = _load()
     W, g, b = _protocol(n_steps, waveform, dirs, bvals)

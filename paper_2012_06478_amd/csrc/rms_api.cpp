@@ -103,6 +103,36 @@ int build_tables(const rms_substrate& sub, const double* D, const double* kappa,
     return RMS_OK;
 }
 
+// Saturation thresholds at absorbing membranes (magnetization transfer, end
+// of section 2.1.3): a walker in label a meeting label b is saturated with
+// P_MT = rho[a][b] ds_a C_3 / D_a (C_3 of Eq. perm-prob); threshold
+// floor(P_MT 2^32).  No table (the plain kernels) when no face absorbs.
+int build_mt_table(const rms_substrate& sub, const double* D, const double* rho, double dt,
+                   RunSetup& t) {
+    const int L = sub.n_labels;
+    const double C3 = 2.0 / 3.0;
+    t.thr_mt.assign(static_cast<size_t>(L) * L, 0u);
+    bool any = false;
+    for (int a = 0; a < L; ++a) {
+        for (int b = 0; b < L; ++b) {
+            const double r = rho[static_cast<size_t>(a) * L + b];
+            if (!(r >= 0.0) || !std::isfinite(r))
+                return fail(RMS_E_INVALID_ARG, "rho must be finite and >= 0");
+            if (a == b || sub.dead[a] || r == 0.0) continue;
+            const double P = std::min(1.0, r * std::sqrt(6.0 * D[a] * dt) * C3 / D[a]);
+            if (P > RMS_MAX_PERM_PROB)
+                return fail(RMS_E_PROB_TOO_LARGE,
+                            "saturation probability " + std::to_string(P) +
+                                " > RMS_MAX_PERM_PROB (0.1): lower dt or rho");
+            const uint32_t th = static_cast<uint32_t>(std::floor(std::ldexp(P, 32)));
+            t.thr_mt[static_cast<size_t>(a) * L + b] = th;
+            any |= th != 0u;
+        }
+    }
+    if (!any) t.thr_mt.clear();
+    return RMS_OK;
+}
+
 // Multiplier and shift for exact division of n < 2^31 by d >= 1:
 // n / d == (n m) >> sh with sh = 31 + ceil(log2 d), m = ceil(2^sh / d) < 2^32.
 void div_magic(uint32_t d, uint32_t* m, uint32_t* sh) {
@@ -168,6 +198,10 @@ int prepare_run(const rms_substrate* sub, const rms_params* params, uint64_t see
     }
     int rc = build_tables(*sub, D, kappa, T2, dt_ms, r);
     if (rc) return rc;
+    if (params && params->rho) {
+        rc = build_mt_table(*sub, D, params->rho, dt_ms, r);
+        if (rc) return rc;
+    }
 
     // waveform scale: phi = sum_k Q_k g.dx_k with Q_k = dt sum_{i>=k} G_i, so the
     // discrete b of a unit shape is dt sum_k Q_k^2 (section 2.3, Eq. signal)
@@ -228,6 +262,7 @@ int prepare_run(const rms_substrate* sub, const rms_params* params, uint64_t see
 size_t device_bytes(const RunSetup& r, bool resumable) {
     const size_t L = static_cast<size_t>(r.sub->n_labels);
     size_t b = L * (2 * sizeof(double) + 2 * sizeof(float)) + L * L * sizeof(uint32_t);
+    b += r.thr_mt.size() * sizeof(uint32_t);
     b += r.gdt.size() * sizeof(double) + 2 * kTrigSize * sizeof(double);
     b += static_cast<size_t>(r.n_walkers) * r.width * sizeof(double);
     b += r.kg.size() * sizeof(double) + r.sig_shape.size() * sizeof(int);
@@ -237,7 +272,7 @@ size_t device_bytes(const RunSetup& r, bool resumable) {
         b += static_cast<size_t>(r.n_walkers) *
              walker_state_bytes(r.precision, r.sub->label_bytes, r.n_shapes);
     b += order_bytes(r.n_walkers);
-    if (!resumable && seg_state_bytes(r.precision, r.n_shapes, r.n_walkers) > 0)
+    if (!resumable && r.thr_mt.empty() && seg_state_bytes(r.precision, r.n_shapes, r.n_walkers) > 0)
         b += seg_state_bytes(r.precision, r.n_shapes, r.n_walkers) + seg_ctl_bytes(r.n_walkers);
     return b + 64 * 1024;  // allocation granularity slack
 }
@@ -259,6 +294,7 @@ int DeviceRun::create(const rms_substrate& sub, const RunSetup& r, bool resumabl
     const size_t o_sigma_f = take(L * sizeof(float));
     const size_t o_it2_f = take(L * sizeof(float));
     const size_t o_thr = take(L * L * sizeof(uint32_t));
+    const size_t o_thr_mt = take(r.thr_mt.size() * sizeof(uint32_t));
     const size_t o_gdt = take(r.gdt.size() * sizeof(double));
     const size_t o_trig = take(2 * kTrigSize * sizeof(double));
     const size_t o_wstate = take(static_cast<size_t>(r.n_walkers) * r.width * sizeof(double));
@@ -274,7 +310,10 @@ int DeviceRun::create(const rms_substrate& sub, const RunSetup& r, bool resumabl
     const size_t o_state = take(state_b);
     const size_t order_b = order_bytes(r.n_walkers);
     const size_t o_order = take(order_b);
-    const size_t seg_b = resumable ? 0 : seg_state_bytes(r.precision, r.n_shapes, r.n_walkers);
+    // absorbing membranes run the one-launch kernel, without the persistent walk's buffers
+    const size_t seg_b = resumable || !r.thr_mt.empty()
+                             ? 0
+                             : seg_state_bytes(r.precision, r.n_shapes, r.n_walkers);
     const size_t o_seg_state = take(seg_b);
     const size_t o_seg_ctl = take(seg_b > 0 ? seg_ctl_bytes(r.n_walkers) : 0);
     void* base = nullptr;
@@ -286,6 +325,7 @@ int DeviceRun::create(const rms_substrate& sub, const RunSetup& r, bool resumabl
     float* d_sigma_f = reinterpret_cast<float*>(b + o_sigma_f);
     float* d_it2_f = reinterpret_cast<float*>(b + o_it2_f);
     uint32_t* d_thr = reinterpret_cast<uint32_t*>(b + o_thr);
+    uint32_t* d_thr_mt = r.thr_mt.empty() ? nullptr : reinterpret_cast<uint32_t*>(b + o_thr_mt);
     double* d_gdt = reinterpret_cast<double*>(b + o_gdt);
     double* d_trig = reinterpret_cast<double*>(b + o_trig);
     double* d_wstate = reinterpret_cast<double*>(b + o_wstate);
@@ -304,6 +344,7 @@ int DeviceRun::create(const rms_substrate& sub, const RunSetup& r, bool resumabl
     RMS_HIP(upload(d_sigma_f, r.sigma_f, s));
     RMS_HIP(upload(d_it2_f, r.inv_t2_f, s));
     RMS_HIP(upload(d_thr, r.thr, s));
+    if (d_thr_mt) RMS_HIP(upload(d_thr_mt, r.thr_mt, s));
     RMS_HIP(upload(d_gdt, r.gdt, s));
     RMS_HIP(upload(d_trig, r.trig, s));
     RMS_HIP(upload(d_kg, r.kg, s));
@@ -328,6 +369,7 @@ int DeviceRun::create(const rms_substrate& sub, const RunSetup& r, bool resumabl
     wp.sigma = d_sigma;
     wp.inv_t2 = d_it2;
     wp.thr = d_thr;
+    wp.thr_mt = d_thr_mt;
     wp.sigma_f = d_sigma_f;
     wp.inv_t2_f = d_it2_f;
     wp.seed = r.seed;
@@ -674,7 +716,8 @@ int rms_run_record(const rms_substrate* sub, const rms_params* params, uint64_t 
                                            static_cast<uint32_t>(e),
                                            e < n_steps ? rms::kItemRecord : 0u, stream));
             RMS_HIP(rms::launch_walk_packed(d_items, n_items, d_plan, precision,
-                                            sub->dev_label_bytes, r.n_shapes, stream));
+                                            sub->dev_label_bytes, r.n_shapes, !r.thr_mt.empty(),
+                                            stream));
             b = e;
         }
         if (k < n_rec) RMS_HIP(record(k));

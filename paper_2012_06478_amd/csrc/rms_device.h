@@ -146,6 +146,15 @@ __device__ __forceinline__ uint4 rare_block(uint32_t i0, const Ids& id) {
     return philox4x32_10(c, 3u, id.wlo, id.whi, id.k0, id.k1);
 }
 
+// Block of substream 4 for step index i0: the saturation words of the step's
+// first to third membrane met, read only where membranes absorb (end of
+// section 2.1.3); computed on that branch, like rare_block.
+__device__ __forceinline__ uint4 mt_block(uint32_t i0, const Ids& id) {
+    uint32_t c = i0;
+    asm volatile("" : "+v"(c));
+    return philox4x32_10(c, 4u, id.wlo, id.whi, id.k0, id.k1);
+}
+
 // n / d for n < 2^31 as (n m) >> sh with m = ceil(2^sh / d), sh = 31 +
 // ceil(log2 d): exact, because the error n (m - 2^sh/d) / 2^sh stays below
 // 2^-ceil(log2 d) <= 1/d.  m and sh come from the host.
@@ -254,6 +263,14 @@ __device__ __forceinline__ uint32_t threshold(const WalkPlan& p, int l, int nl) 
     return *reinterpret_cast<const uint32_t*>(reinterpret_cast<const char*>(p.thr) + off);
 }
 
+// Saturation threshold for a walker in label l meeting label nl at an
+// absorbing membrane (0: the face does not absorb); layout as threshold().
+__device__ __forceinline__ uint32_t threshold_mt(const WalkPlan& p, int l, int nl) {
+    const uint32_t off = (__umul24(static_cast<uint32_t>(l), static_cast<uint32_t>(p.n_labels)) +
+                          static_cast<uint32_t>(nl)) * 4u;
+    return *reinterpret_cast<const uint32_t*>(reinterpret_cast<const char*>(p.thr_mt) + off);
+}
+
 // Entry at byte offset `off` of the padded label volume.  Offsets stay below
 // 2^32 (fewer than 2^31 entries of at most two bytes), so the load takes a
 // 32-bit offset from the volume's base and needs no 64-bit address arithmetic.
@@ -286,8 +303,12 @@ __device__ __forceinline__ Start draw_start(const WalkPlan& p, const Ids& id) {
 // ---------------------------------------------------------------------------
 // Double-precision form.
 // ---------------------------------------------------------------------------
-template <typename LabelT, int NS>
-struct WalkerF64 {
+// MT: membranes may absorb (magnetization transfer, end of section 2.1.3):
+// at a membrane hit, before the permeation decision, a walker is saturated
+// with the pair's probability and keeps walking with weight 0 (Eq. wt-mt),
+// held as R = infinity.  Without MT that code is not compiled.
+template <typename LabelT, int NS, bool MT>
+struct WalkerF64T {
     static constexpr int kShapes = NS > 0 ? NS : 1;
     static constexpr bool kTrig = true;  // direction from the LDS angle table
     static constexpr int kWaves = 5;     // waves per SIMD the persistent walk asks for
@@ -371,6 +392,8 @@ struct WalkerF64 {
         uint32_t rawc = 0;  // entry of the voxel last passed into (its halo flags)
         int mw_used = 0;
         uint4 mw;  // words of substream 3, computed before the second membrane hit reads them
+        [[maybe_unused]] uint4 mtw;  // words of substream 4 (absorbing membranes)
+        [[maybe_unused]] bool have_mtw = false;
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
             if (k < nev) {
@@ -384,6 +407,17 @@ struct WalkerF64 {
                 bool cross = true;
                 if (nl != l) {
                     ++nhit;
+                    if constexpr (MT) {
+                        const uint32_t tm = threshold_mt(p, l, nl);
+                        if (tm != 0u) {
+                            if (!have_mtw) {
+                                mtw = mt_block(i0, id);
+                                have_mtw = true;
+                            }
+                            const uint32_t u = mw_used == 0 ? mtw.x : (mw_used == 1 ? mtw.y : mtw.z);
+                            if (u < tm) R = INFINITY;  // saturated: weight 0 from here on
+                        }
+                    }
                     if (mw_used == 1) mw = rare_block(i0, id);
                     const uint32_t word = mw_used == 0 ? m1 : (mw_used == 1 ? mw.x : mw.y);
                     ++mw_used;
@@ -470,6 +504,11 @@ struct WalkerF64 {
     }
 };
 
+template <typename LabelT, int NS>
+using WalkerF64 = WalkerF64T<LabelT, NS, false>;
+template <typename LabelT, int NS>
+using WalkerF64MT = WalkerF64T<LabelT, NS, true>;
+
 // ---------------------------------------------------------------------------
 // Mixed-precision form.
 // ---------------------------------------------------------------------------
@@ -478,8 +517,8 @@ __device__ __forceinline__ float unit_open_f(uint32_t w) {
     return static_cast<float>(unit_open(w));
 }
 
-template <typename LabelT, int NS>
-struct WalkerMixed {
+template <typename LabelT, int NS, bool MT>
+struct WalkerMixedT {
     static constexpr int kShapes = NS > 0 ? NS : 1;
     static constexpr bool kTrig = false;  // hardware sine and cosine
     static constexpr int kWaves = 6;      // waves per SIMD the persistent walk asks for
@@ -566,6 +605,8 @@ struct WalkerMixed {
         uint32_t rawc = 0;  // entry of the voxel last passed into (its halo flags)
         int mw_used = 0;
         uint4 mw;  // words of substream 3, computed before the second membrane hit reads them
+        [[maybe_unused]] uint4 mtw;  // words of substream 4 (absorbing membranes)
+        [[maybe_unused]] bool have_mtw = false;
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
             if (k < nev) {
@@ -579,6 +620,17 @@ struct WalkerMixed {
                 bool cross = true;
                 if (nl != l) {
                     ++nhit;
+                    if constexpr (MT) {
+                        const uint32_t tm = threshold_mt(p, l, nl);
+                        if (tm != 0u) {
+                            if (!have_mtw) {
+                                mtw = mt_block(i0, id);
+                                have_mtw = true;
+                            }
+                            const uint32_t u = mw_used == 0 ? mtw.x : (mw_used == 1 ? mtw.y : mtw.z);
+                            if (u < tm) R = INFINITY;  // saturated: weight 0 from here on
+                        }
+                    }
                     if (mw_used == 1) mw = rare_block(i0, id);
                     const uint32_t word = mw_used == 0 ? m1 : (mw_used == 1 ? mw.x : mw.y);
                     ++mw_used;
@@ -665,6 +717,11 @@ struct WalkerMixed {
                     ph[q][a] * p.voxel_um;
     }
 };
+
+template <typename LabelT, int NS>
+using WalkerMixed = WalkerMixedT<LabelT, NS, false>;
+template <typename LabelT, int NS>
+using WalkerMixedMT = WalkerMixedT<LabelT, NS, true>;
 
 // Steps [b, e) of one walker: direction words two steps per Philox block,
 // first membrane words four steps per block, both blocks computed under

@@ -59,6 +59,7 @@ struct RunSetup {
     std::vector<double> sigma, inv_t2;
     std::vector<float> sigma_f, inv_t2_f;
     std::vector<uint32_t> thr;
+    std::vector<uint32_t> thr_mt;  // saturation thresholds (end of section 2.1.3), or empty
     double max_sigma = 0.0, max_p = 0.0;
     std::vector<double> gdt;
     std::vector<double> trig;  // [kTrigSize][2] angle table (fill_trig_table)

@@ -36,6 +36,8 @@ struct WalkPlan {
     const double* sigma;    // [n_labels] step length per label, voxel units
     const double* inv_t2;   // [n_labels] 1/T2 (0 for none)
     const uint32_t* thr;    // [n_labels^2] permeation thresholds: word < thr permeates
+    const uint32_t* thr_mt; // [n_labels^2] saturation thresholds at absorbing membranes, or
+                            // null: no membrane absorbs
     const float* sigma_f;   // fp32 copies for the mixed form
     const float* inv_t2_f;
     uint64_t seed;
@@ -103,13 +105,14 @@ constexpr int kAccFixed = 25;  // alpha, 6 M2, 15 M4, 3 counters
 
 // Whole walk of every walker of one run (precision RMS_FP64 or RMS_MIXED).
 hipError_t launch_walk(const WalkPlan& p, int precision, hipStream_t s);
-// A packed launch over several runs that share precision, label width and
-// shape count: each block advances its walkers by a range of steps, starting
+// A packed launch over several runs that share precision, label width, shape
+// count and whether membranes absorb (mt: every plan has thr_mt): each block advances its walkers by a range of steps, starting
 // from the stored state (or the start when step_begin == 0) and storing the
 // state again (or the final record when step_end == n_steps; with kItemRecord
 // the record as well).
 hipError_t launch_walk_packed(const PackedItem* items, int n_items, const WalkPlan* plans,
-                              int precision, int label_bytes, int n_shapes, hipStream_t s);
+                              int precision, int label_bytes, int n_shapes, bool mt,
+                              hipStream_t s);
 // Sets the step range and flags of items[0, n_items) on the device.
 hipError_t launch_item_range(PackedItem* items, int n_items, uint32_t step_begin,
                              uint32_t step_end, uint32_t flags, hipStream_t s);

@@ -6,7 +6,8 @@
 //      the budget (buffers allocated and inputs uploaded on the server's
 //      stream);
 //   2. build one work list per group of admitted requests that share
-//      precision, label width and shape count: a block per 256 walkers of each
+//      precision, label width, shape count and whether membranes absorb: a
+//      block per 256 walkers of each
 //      request, each advancing its walkers from the request's current step by
 //      the slice length (or to the end);
 //   3. run the packed walk launches (walker states stay in HBM between
@@ -158,13 +159,16 @@ void rms_server::loop() {
         if (S <= 0) S = std::max<int64_t>(64, std::min<int64_t>(1 << 20, 4000000000LL / walkers));
         S = (S + 3) / 4 * 4;  // slices start on a multiple of 4 steps (both Philox streams)
 
-        // one packed launch per (precision, label width, shape count)
-        std::map<std::tuple<int, int, int>, std::vector<Request*>> groups;
+        // one packed launch per (precision, label width, shape count, absorbing)
+        std::map<std::tuple<int, int, int, bool>, std::vector<Request*>> groups;
         for (Request* r : active)
-            groups[{r->setup.precision, r->setup.sub->dev_label_bytes, r->setup.n_shapes}].push_back(r);
+            groups[{r->setup.precision, r->setup.sub->dev_label_bytes, r->setup.n_shapes,
+                    !r->setup.thr_mt.empty()}]
+                .push_back(r);
         std::vector<rms::WalkPlan> plans;
         std::vector<rms::PackedItem> items;
-        std::vector<std::tuple<int, int, int, size_t, size_t>> launches_todo;  // key, item range
+        // key, item range
+        std::vector<std::tuple<int, int, int, bool, size_t, size_t>> launches_todo;
         std::vector<int64_t> step_end(active.size());
         std::map<Request*, size_t> index;
         for (size_t i = 0; i < active.size(); ++i) index[active[i]] = i;
@@ -189,7 +193,8 @@ void rms_server::loop() {
                                                     static_cast<uint32_t>(e), 0u});
             }
             launches_todo.emplace_back(std::get<0>(g.first), std::get<1>(g.first),
-                                       std::get<2>(g.first), first, items.size() - first);
+                                       std::get<2>(g.first), std::get<3>(g.first), first,
+                                       items.size() - first);
         }
         hipError_t e = grow(&d_items, &items_cap, items.size(), stream);
         if (e == hipSuccess) e = grow(&d_plans, &plans_cap, plans.size(), stream);
@@ -202,9 +207,9 @@ void rms_server::loop() {
         if (e == hipSuccess) e = hipEventRecord(ev0, stream);
         for (auto& L : launches_todo) {
             if (e != hipSuccess) break;
-            e = rms::launch_walk_packed(d_items + std::get<3>(L), static_cast<int>(std::get<4>(L)),
+            e = rms::launch_walk_packed(d_items + std::get<4>(L), static_cast<int>(std::get<5>(L)),
                                         d_plans, std::get<0>(L), std::get<1>(L), std::get<2>(L),
-                                        stream);
+                                        std::get<3>(L), stream);
         }
         if (e == hipSuccess) e = hipEventRecord(ev1, stream);
         if (e == hipSuccess) e = hipStreamSynchronize(stream);

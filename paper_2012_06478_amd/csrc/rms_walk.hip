@@ -461,6 +461,13 @@ hipError_t launch_order(const WalkPlan& p, hipStream_t s) {
 hipError_t launch_walk(const WalkPlan& p, int precision, hipStream_t s) {
     if (p.n_walkers <= 0) return hipSuccess;
     const bool u8 = p.label_bytes == 1;
+    if (p.thr_mt) {  // absorbing membranes: the one-launch kernel only
+        if (precision == RMS_FP64)
+            return u8 ? run_ns<dev::WalkerF64MT, uint8_t>(p, s)
+                      : run_ns<dev::WalkerF64MT, uint16_t>(p, s);
+        return u8 ? run_ns<dev::WalkerMixedMT, uint8_t>(p, s)
+                  : run_ns<dev::WalkerMixedMT, uint16_t>(p, s);
+    }
     if (p.order && p.seg_state && p.seg_ctl) {
         if (precision == RMS_FP64)
             return u8 ? run_seg_ns<dev::WalkerF64, uint8_t>(p, s)
@@ -482,9 +489,17 @@ hipError_t launch_item_range(PackedItem* items, int n_items, uint32_t step_begin
 }
 
 hipError_t launch_walk_packed(const PackedItem* items, int n_items, const WalkPlan* plans,
-                              int precision, int label_bytes, int n_shapes, hipStream_t s) {
+                              int precision, int label_bytes, int n_shapes, bool mt,
+                              hipStream_t s) {
     if (n_items <= 0) return hipSuccess;
     const bool u8 = label_bytes == 1;
+    if (mt) {
+        if (precision == RMS_FP64)
+            return u8 ? packed_ns<dev::WalkerF64MT, uint8_t>(items, n_items, plans, n_shapes, s)
+                      : packed_ns<dev::WalkerF64MT, uint16_t>(items, n_items, plans, n_shapes, s);
+        return u8 ? packed_ns<dev::WalkerMixedMT, uint8_t>(items, n_items, plans, n_shapes, s)
+                  : packed_ns<dev::WalkerMixedMT, uint16_t>(items, n_items, plans, n_shapes, s);
+    }
     if (precision == RMS_FP64)
         return u8 ? packed_ns<dev::WalkerF64, uint8_t>(items, n_items, plans, n_shapes, s)
                   : packed_ns<dev::WalkerF64, uint16_t>(items, n_items, plans, n_shapes, s);
