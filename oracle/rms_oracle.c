@@ -23,9 +23,9 @@
  *                    two or three membranes met in one step) use words 0 and 1
  *                    of block i-1;
  *       substream 2: the walker's start, blocks 0 and 1;
- *       substream 4: the saturation decisions at absorbing membranes of step i
- *                    (first to third membrane met) use words 0 to 2 of block
- *                    i-1;
+ *       saturation at absorbing membranes: the first membrane met in step i
+ *                    uses word (i-1) mod 4 of substream 4 block (i-1)/4, the
+ *                    second and third words 2 and 3 of substream 3 block i-1;
  *   - a word w maps to the uniform deviate (w + 1/2) 2^-32, exact in FP64;
  *   - the volume is periodic; displacements are unwrapped;
  *   - after a permeation into a compartment of different diffusivity the
@@ -38,8 +38,8 @@
  *   - moments recorded at an earlier step t (D(t) and K(t), section 2.3) weight
  *     each walker by alpha(t) = exp(-R(t)), the T2 integral up to that step;
  *   - an absorbing membrane (magnetization transfer, end of section 2.1.3)
- *     saturates a walker that meets it with probability P_MT, decided before
- *     and independently of the permeation decision at the same face; the
+ *     saturates a walker that meets it with probability P_MT, decided at the
+ *     face with a word of its own, independent of the permeation word; the
  *     saturated walker keeps walking with weight 0 (Eq. wt-mt), held as
  *     R = infinity so that alpha = exp(-R) = 0.
  *
@@ -350,9 +350,13 @@ typedef struct {
 static uint32_t philox_mw(void* p, int k) {
     const philox_mw_ctx* c = (const philox_mw_ctx*)p;
     uint32_t w[4];
-    if (k >= 16) {
-        philox_block(c->seed, c->index, 4u, c->walker, w);
-        return w[k - 16];
+    if (k == 16) {
+        philox_block(c->seed, c->index / 4u, 4u, c->walker, w);
+        return w[c->index % 4u];
+    }
+    if (k > 16) {
+        philox_block(c->seed, c->index, 3u, c->walker, w);
+        return w[k - 15];
     }
     if (k == 0) {
         philox_block(c->seed, c->index / 4u, 1u, c->walker, w);
