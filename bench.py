@@ -326,6 +326,48 @@ def record_report(args):
     print(json.dumps(line), flush=True)
 
 
+def mt_report(args):
+    """Absorbing membranes (magnetization transfer, end of section 2.1.3): the
+    workload with every cell absorbing at its faces to the extracellular label
+    (surface relaxivity ``--mt`` um/ms, both sides), against the same run
+    without; reports both throughputs and the weight lost to saturation."""
+    import torch
+    import paper_2012_06478_amd as rms
+    assert torch.cuda.is_available(), "bench needs a GPU"
+    torch.cuda.set_device(0)
+    log(f"[mt] building workload {args.workload}")
+    c = workload(args.workload)
+    prec = rms.RMS_FP64 if args.precision == "fp64" else rms.RMS_MIXED
+    sub = rms.rms_create_substrate(c["labels"], c["voxel_um"], c["D"], c["kappa"], c["T2"],
+                                   c.get("dead"))
+    L = len(c["D"])
+    rho = np.zeros((L, L))
+    rho[1:, 0] = args.mt
+    rho[0, 1:] = args.mt
+    P = dict(D=c["D"], kappa=c["kappa"], T2=c["T2"], rho=rho)
+    run = dict(seed=c["seed"], n_walkers=c["n_walkers"], n_steps=c["n_steps"], dt=c["dt"],
+               waveform=c["waveform"], dirs=c["dirs"], bvals=c["bvals"], precision=prec)
+    rms.rms_run(sub, **run)  # warm-up of both paths
+    rms.rms_run(sub, params=P, **run)
+    plain = [rms.rms_run(sub, **run) for _ in range(args.steps)]
+    mt = [rms.rms_run(sub, params=P, **run) for _ in range(args.steps)]
+    sub.close()
+    ws = c["n_walkers"] * c["n_steps"]
+    line = {
+        "metric": "walker-steps/s with absorbing membranes", "unit": "walker-steps/s",
+        "value": ws / min(r["wall_s"] for r in mt), "higher_is_better": True,
+        "data": "synthetic", "workload": c["name"], "precision": args.precision,
+        "rho_um_per_ms": args.mt,
+        "plain_walker_steps_per_s": ws / min(r["wall_s"] for r in plain),
+        "kernel_ms_mt": min(r["kernel_ms"] for r in mt),
+        "kernel_ms_plain": min(r["kernel_ms"] for r in plain),
+        "weight_kept": mt[0]["sum_alpha"] / plain[0]["sum_alpha"],
+        "S_b_max_dir0_mt": [float(mt[0]["signal"][0, -1, 0].real),
+                            float(mt[0]["signal"][0, -1, 0].imag)],
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -346,6 +388,9 @@ def main():
     ap.add_argument("--records", type=int, default=0,
                     help="time series of D and K: record the moments at this many steps and "
                          "report the recorded run's throughput against the plain one")
+    ap.add_argument("--mt", type=float, default=0.0,
+                    help="absorbing membranes: surface relaxivity (um/ms) of every cell face; "
+                         "reports the run against the plain one")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run only a plain 1 GiB device copy (3 times), to scale the "
                          "FETCH_SIZE/WRITE_SIZE counters")
@@ -360,6 +405,9 @@ def main():
         return
     if args.records > 0:
         record_report(args)
+        return
+    if args.mt > 0:
+        mt_report(args)
         return
     if args.serve:
         if args.precision == "fp64" and "--precision" not in sys.argv:

@@ -91,9 +91,8 @@ typedef struct rms_substrate rms_substrate;
  *          RMS_E_PROB_TOO_LARGE), decided at the membrane before and
  *          independently of the permeation decision, and keeps walking with
  *          weight 0 (Eq. wt-mt; its R becomes INFINITY in walker_dump).  NULL
- *          or all zero: no membrane absorbs.  A run with absorbing membranes
- *          walks in one launch (not the persistent walk).  If every walker is
- *          saturated, sum_alpha is 0 and the normalized results are NaN. */
+ *          or all zero: no membrane absorbs.  If every walker is saturated,
+ *          sum_alpha is 0 and the normalized results are NaN. */
 typedef struct {
     int n_labels;
     const double* D;

@@ -272,7 +272,7 @@ size_t device_bytes(const RunSetup& r, bool resumable) {
         b += static_cast<size_t>(r.n_walkers) *
              walker_state_bytes(r.precision, r.sub->label_bytes, r.n_shapes);
     b += order_bytes(r.n_walkers);
-    if (!resumable && r.thr_mt.empty() && seg_state_bytes(r.precision, r.n_shapes, r.n_walkers) > 0)
+    if (!resumable && seg_state_bytes(r.precision, r.n_shapes, r.n_walkers) > 0)
         b += seg_state_bytes(r.precision, r.n_shapes, r.n_walkers) + seg_ctl_bytes(r.n_walkers);
     return b + 64 * 1024;  // allocation granularity slack
 }
@@ -310,10 +310,7 @@ int DeviceRun::create(const rms_substrate& sub, const RunSetup& r, bool resumabl
     const size_t o_state = take(state_b);
     const size_t order_b = order_bytes(r.n_walkers);
     const size_t o_order = take(order_b);
-    // absorbing membranes run the one-launch kernel, without the persistent walk's buffers
-    const size_t seg_b = resumable || !r.thr_mt.empty()
-                             ? 0
-                             : seg_state_bytes(r.precision, r.n_shapes, r.n_walkers);
+    const size_t seg_b = resumable ? 0 : seg_state_bytes(r.precision, r.n_shapes, r.n_walkers);
     const size_t o_seg_state = take(seg_b);
     const size_t o_seg_ctl = take(seg_b > 0 ? seg_ctl_bytes(r.n_walkers) : 0);
     void* base = nullptr;

@@ -146,15 +146,6 @@ __device__ __forceinline__ uint4 rare_block(uint32_t i0, const Ids& id) {
     return philox4x32_10(c, 3u, id.wlo, id.whi, id.k0, id.k1);
 }
 
-// Block of substream 4 for step index i0: the saturation words of the step's
-// first to third membrane met, read only where membranes absorb (end of
-// section 2.1.3); computed on that branch, like rare_block.
-__device__ __forceinline__ uint4 mt_block(uint32_t i0, const Ids& id) {
-    uint32_t c = i0;
-    asm volatile("" : "+v"(c));
-    return philox4x32_10(c, 4u, id.wlo, id.whi, id.k0, id.k1);
-}
-
 // n / d for n < 2^31 as (n m) >> sh with m = ceil(2^sh / d), sh = 31 +
 // ceil(log2 d): exact, because the error n (m - 2^sh/d) / 2^sh stays below
 // 2^-ceil(log2 d) <= 1/d.  m and sh come from the host.
@@ -304,14 +295,18 @@ __device__ __forceinline__ Start draw_start(const WalkPlan& p, const Ids& id) {
 // Double-precision form.
 // ---------------------------------------------------------------------------
 // MT: membranes may absorb (magnetization transfer, end of section 2.1.3):
-// at a membrane hit, before the permeation decision, a walker is saturated
-// with the pair's probability and keeps walking with weight 0 (Eq. wt-mt),
-// held as R = infinity.  Without MT that code is not compiled.
+// at a membrane hit a walker is saturated with the pair's probability, by a
+// word of its own (the first membrane of step i: word (i-1) mod 4 of
+// substream 4 block (i-1)/4, computed for the wave with the first membrane
+// block; the second and third: words 2 and 3 of the substream-3 block), and
+// keeps walking with weight 0 (Eq. wt-mt), held as R = infinity.  Without MT
+// that code is not compiled.
 template <typename LabelT, int NS, bool MT>
 struct WalkerF64T {
     static constexpr int kShapes = NS > 0 ? NS : 1;
     static constexpr bool kTrig = true;  // direction from the LDS angle table
     static constexpr int kWaves = 5;     // waves per SIMD the persistent walk asks for
+    static constexpr bool kMT = MT;
     uint32_t lb;     // byte offset of the voxel's entry in the padded volume
     int l, l0;       // label, label at the start
     uint32_t nface, nhit, nperm;
@@ -342,6 +337,7 @@ struct WalkerF64T {
     // membrane word m1.
     __device__ __forceinline__ void step(const WalkPlan& p, const LabelT* __restrict__ lab,
                                          uint32_t i0, uint32_t wa, uint32_t wb, uint32_t m1,
+                                         [[maybe_unused]] uint32_t t1,
                                          const Ids& id, const double* trig) {
         const double u1 = unit_open(wa);
         double sn, cs;  // of 2 pi u2, u2 = unit_open(wb)
@@ -392,8 +388,6 @@ struct WalkerF64T {
         uint32_t rawc = 0;  // entry of the voxel last passed into (its halo flags)
         int mw_used = 0;
         uint4 mw;  // words of substream 3, computed before the second membrane hit reads them
-        [[maybe_unused]] uint4 mtw;  // words of substream 4 (absorbing membranes)
-        [[maybe_unused]] bool have_mtw = false;
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
             if (k < nev) {
@@ -407,21 +401,20 @@ struct WalkerF64T {
                 bool cross = true;
                 if (nl != l) {
                     ++nhit;
-                    if constexpr (MT) {
-                        const uint32_t tm = threshold_mt(p, l, nl);
-                        if (tm != 0u) {
-                            if (!have_mtw) {
-                                mtw = mt_block(i0, id);
-                                have_mtw = true;
-                            }
-                            const uint32_t u = mw_used == 0 ? mtw.x : (mw_used == 1 ? mtw.y : mtw.z);
-                            if (u < tm) R = INFINITY;  // saturated: weight 0 from here on
-                        }
+                    [[maybe_unused]] uint32_t tp = 0u, tm = 0u;
+                    if constexpr (MT) {  // both thresholds in one memory round trip
+                        tp = threshold(p, l, nl);
+                        tm = threshold_mt(p, l, nl);
                     }
                     if (mw_used == 1) mw = rare_block(i0, id);
+                    if constexpr (MT) {
+                        const uint32_t u = mw_used == 0 ? t1 : (mw_used == 1 ? mw.z : mw.w);
+                        if (u < tm) R = INFINITY;  // saturated: weight 0 from here on
+                    }
                     const uint32_t word = mw_used == 0 ? m1 : (mw_used == 1 ? mw.x : mw.y);
                     ++mw_used;
-                    cross = word < threshold(p, l, nl);
+                    if constexpr (MT) cross = word < tp;
+                    else cross = word < threshold(p, l, nl);
                     if (cross) {
                         ++nperm;
                         const double ek = fmax(face_len(a), P);
@@ -522,6 +515,7 @@ struct WalkerMixedT {
     static constexpr int kShapes = NS > 0 ? NS : 1;
     static constexpr bool kTrig = false;  // hardware sine and cosine
     static constexpr int kWaves = 6;      // waves per SIMD the persistent walk asks for
+    static constexpr bool kMT = MT;
     uint32_t lb;  // byte offset of the voxel's entry in the padded volume
     int l, l0;
     uint32_t nface, nhit, nperm;
@@ -553,6 +547,7 @@ struct WalkerMixedT {
 
     __device__ __forceinline__ void step(const WalkPlan& p, const LabelT* __restrict__ lab,
                                          uint32_t i0, uint32_t wa, uint32_t wb, uint32_t m1,
+                                         [[maybe_unused]] uint32_t t1,
                                          const Ids& id, const double* trig) {
         // uniform deviates from the top 24 bits of each word: (k + 1/2) 2^-24
         const float u1 = fmaf(static_cast<float>(wa >> 8), 0x1p-24f, 0x1p-25f);
@@ -605,8 +600,6 @@ struct WalkerMixedT {
         uint32_t rawc = 0;  // entry of the voxel last passed into (its halo flags)
         int mw_used = 0;
         uint4 mw;  // words of substream 3, computed before the second membrane hit reads them
-        [[maybe_unused]] uint4 mtw;  // words of substream 4 (absorbing membranes)
-        [[maybe_unused]] bool have_mtw = false;
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
             if (k < nev) {
@@ -620,21 +613,20 @@ struct WalkerMixedT {
                 bool cross = true;
                 if (nl != l) {
                     ++nhit;
-                    if constexpr (MT) {
-                        const uint32_t tm = threshold_mt(p, l, nl);
-                        if (tm != 0u) {
-                            if (!have_mtw) {
-                                mtw = mt_block(i0, id);
-                                have_mtw = true;
-                            }
-                            const uint32_t u = mw_used == 0 ? mtw.x : (mw_used == 1 ? mtw.y : mtw.z);
-                            if (u < tm) R = INFINITY;  // saturated: weight 0 from here on
-                        }
+                    [[maybe_unused]] uint32_t tp = 0u, tm = 0u;
+                    if constexpr (MT) {  // both thresholds in one memory round trip
+                        tp = threshold(p, l, nl);
+                        tm = threshold_mt(p, l, nl);
                     }
                     if (mw_used == 1) mw = rare_block(i0, id);
+                    if constexpr (MT) {
+                        const uint32_t u = mw_used == 0 ? t1 : (mw_used == 1 ? mw.z : mw.w);
+                        if (u < tm) R = INFINITY;  // saturated: weight 0 from here on
+                    }
                     const uint32_t word = mw_used == 0 ? m1 : (mw_used == 1 ? mw.x : mw.y);
                     ++mw_used;
-                    cross = word < threshold(p, l, nl);
+                    if constexpr (MT) cross = word < tp;
+                    else cross = word < threshold(p, l, nl);
                     if (cross) {
                         ++nperm;
                         const float ek = fmaxf(face_len(a), P);
@@ -736,17 +728,25 @@ __device__ __forceinline__ void walk_range(const WalkPlan& p, const LabelT* __re
                                            Walker& W, uint32_t b, uint32_t e, const Ids& id,
                                            const double* trig) {
     uint4 wd = make_uint4(0, 0, 0, 0), wm = make_uint4(0, 0, 0, 0);
+    [[maybe_unused]] uint4 wt = make_uint4(0, 0, 0, 0);  // saturation words (MT only)
     if constexpr (kAnyStart) {
         if (b & 1u) wd = philox4x32_10(b >> 1, 0u, id.wlo, id.whi, id.k0, id.k1);
         if (b & 3u) wm = philox4x32_10(b >> 2, 1u, id.wlo, id.whi, id.k0, id.k1);
+        if constexpr (Walker::kMT)
+            if (b & 3u) wt = philox4x32_10(b >> 2, 4u, id.wlo, id.whi, id.k0, id.k1);
     }
     for (uint32_t i0 = b; i0 < e; ++i0) {
         const bool odd = (i0 & 1u) != 0;
         if (!odd) wd = philox4x32_10(i0 >> 1, 0u, id.wlo, id.whi, id.k0, id.k1);
         const uint32_t q = i0 & 3u;
-        if (q == 0) wm = philox4x32_10(i0 >> 2, 1u, id.wlo, id.whi, id.k0, id.k1);
+        if (q == 0) {
+            wm = philox4x32_10(i0 >> 2, 1u, id.wlo, id.whi, id.k0, id.k1);
+            if constexpr (Walker::kMT) wt = philox4x32_10(i0 >> 2, 4u, id.wlo, id.whi, id.k0, id.k1);
+        }
         const uint32_t m1 = q == 0 ? wm.x : (q == 1 ? wm.y : (q == 2 ? wm.z : wm.w));
-        W.step(p, lab, i0, odd ? wd.z : wd.x, odd ? wd.w : wd.y, m1, id, trig);
+        uint32_t t1 = 0u;
+        if constexpr (Walker::kMT) t1 = q == 0 ? wt.x : (q == 1 ? wt.y : (q == 2 ? wt.z : wt.w));
+        W.step(p, lab, i0, odd ? wd.z : wd.x, odd ? wd.w : wd.y, m1, t1, id, trig);
     }
 }
 

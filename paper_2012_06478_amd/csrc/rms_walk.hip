@@ -461,14 +461,22 @@ hipError_t launch_order(const WalkPlan& p, hipStream_t s) {
 hipError_t launch_walk(const WalkPlan& p, int precision, hipStream_t s) {
     if (p.n_walkers <= 0) return hipSuccess;
     const bool u8 = p.label_bytes == 1;
-    if (p.thr_mt) {  // absorbing membranes: the one-launch kernel only
+    const bool seg = p.order && p.seg_state && p.seg_ctl;
+    if (p.thr_mt) {  // absorbing membranes
+        if (seg) {
+            if (precision == RMS_FP64)
+                return u8 ? run_seg_ns<dev::WalkerF64MT, uint8_t>(p, s)
+                          : run_seg_ns<dev::WalkerF64MT, uint16_t>(p, s);
+            return u8 ? run_seg_ns<dev::WalkerMixedMT, uint8_t>(p, s)
+                      : run_seg_ns<dev::WalkerMixedMT, uint16_t>(p, s);
+        }
         if (precision == RMS_FP64)
             return u8 ? run_ns<dev::WalkerF64MT, uint8_t>(p, s)
                       : run_ns<dev::WalkerF64MT, uint16_t>(p, s);
         return u8 ? run_ns<dev::WalkerMixedMT, uint8_t>(p, s)
                   : run_ns<dev::WalkerMixedMT, uint16_t>(p, s);
     }
-    if (p.order && p.seg_state && p.seg_ctl) {
+    if (seg) {
         if (precision == RMS_FP64)
             return u8 ? run_seg_ns<dev::WalkerF64, uint8_t>(p, s)
                       : run_seg_ns<dev::WalkerF64, uint16_t>(p, s);
