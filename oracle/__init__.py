@@ -80,10 +80,13 @@ def _load():
     lib.rmso_run.argtypes = [C.c_void_p, C.c_int, i64_p, C.c_double, C.c_int, d_p, d_p, d_p,
                              u8_p, C.c_uint64, C.c_int64, i64_p, C.c_int64, C.c_double, C.c_int,
                              d_p, C.c_int, d_p, C.c_int, d_p, C.c_int, d_p, d_p, d_p, d_p, d_p,
-                             d_p, d_p, i64_p, d_p, C.c_int, i64_p, d_p, d_p]
+                             d_p, d_p, i64_p, d_p, C.c_int, i64_p, d_p, d_p, d_p, C.c_double,
+                             C.c_int]
     lib.rmso_run.restype = C.c_int
     lib.rmso_mt_prob.argtypes = [C.c_double, C.c_double, C.c_double]
     lib.rmso_mt_prob.restype = C.c_double
+    lib.rmso_conc_perm_probs.argtypes = [C.c_double] * 6 + [C.c_int, C.c_double, d_p, d_p]
+    lib.rmso_conc_perm_probs.restype = None
     _lib = lib
     return lib
 
@@ -124,6 +127,13 @@ def perm_prob(kappa: float, D1: float, D2: float, dt: float) -> float:
 def mt_prob(rho: float, D: float, dt: float) -> float:
     """Saturation probability at an absorbing membrane (end of section 2.1.3)."""
     return _load().rmso_mt_prob(rho, D, dt)
+
+
+def conc_perm_probs(kappa, D1, D2, c1, c2, lam, model, dt):
+    """(P_1->2, P_2->1) across a membrane with spin concentrations (App. C)."""
+    a, b = C.c_double(), C.c_double()
+    _load().rmso_conc_perm_probs(kappa, D1, D2, c1, c2, lam, model, dt, C.byref(a), C.byref(b))
+    return a.value, b.value
 
 
 def tables(D, kappa, T2, dead, dt, voxel_um):
@@ -191,14 +201,17 @@ DUMP_FIELDS = ["dx", "dy", "dz", "R", "label", "ix", "iy", "iz", "ox", "oy", "oz
 
 def run(labels, voxel_um, D, kappa=None, T2=None, dead=None, *, seed, n_walkers, n_steps, dt,
         waveform=None, dirs=None, bvals=None, walker_ids=None, n_threads=None, dump=False,
-        rec_steps=None, rho=None):
+        rec_steps=None, rho=None, conc=None, lam=0.0, perm_model=0):
     """Run the oracle.  ``labels`` is a [nz, ny, nx] uint8/uint16 array (x
     fastest in memory).  Returns a dict of numpy results.  ``rec_steps``
     (ascending steps in 1..n_steps) adds ``records``: sum_alpha, m2, m4, D, K
     after each of those steps (section 2.3, D(t) and K(t)).  ``rho`` [n, n]
     (surface relaxivity, um/ms, for a walker in label a meeting label b) makes
     those membranes absorbing (magnetization transfer, end of section 2.1.3):
-    a saturated walker's R becomes infinite, its weight 0."""
+    a saturated walker's R becomes infinite, its weight 0.  ``conc`` [n]
+    (spin concentration per label), ``lam`` (the exponent of Eq.
+    gen-perm-prob; negative: the minimiser) and ``perm_model`` (0: kappa, 1:
+    Baxter's alternative) follow App. C's general case."""
     lib = _load()
     lab = np.ascontiguousarray(labels)
     if lab.dtype not in (np.uint8, np.uint16):
@@ -232,6 +245,7 @@ def run(labels, voxel_um, D, kappa=None, T2=None, dead=None, *, seed, n_walkers,
     K = 15 + 3 * ns
     wd = np.zeros((n_walkers, K)) if dump else None
     rh = None if rho is None else np.ascontiguousarray(rho, np.float64).reshape(n * n)
+    cc = None if conc is None else np.ascontiguousarray(conc, np.float64)
     rs = None if rec_steps is None else np.ascontiguousarray(rec_steps, np.int64)
     nr = 0 if rs is None else rs.size
     ro = np.zeros(max(nr, 1) * (22 + 2 * nd))
@@ -246,7 +260,8 @@ def run(labels, voxel_um, D, kappa=None, T2=None, dead=None, *, seed, n_walkers,
                       _ptr(Dd, C.c_double), _ptr(Kd, C.c_double), _ptr(sa, C.c_double),
                       _ptr(bd, C.c_double), _ptr(cnt, C.c_int64),
                       None if wd is None else _ptr(wd, C.c_double), nr, _ptr(rs, C.c_int64),
-                      _ptr(ro, C.c_double), _ptr(rh, C.c_double))
+                      _ptr(ro, C.c_double), _ptr(rh, C.c_double), _ptr(cc, C.c_double),
+                      float(lam), int(perm_model))
     if rc:
         raise OracleError(rc)
     out = dict(

@@ -37,6 +37,14 @@
  *   - kurtosis uses moments weighted by alpha and divided by sum(alpha);
  *   - moments recorded at an earlier step t (D(t) and K(t), section 2.3) weight
  *     each walker by alpha(t) = exp(-R(t)), the T2 integral up to that step;
+ *   - unequal spin concentrations c (App. C, general case): walkers start
+ *     with density proportional to c (a uniform voxel draw accepted with
+ *     probability c / max c, attempt j using substream 2 blocks 2j and 2j+1,
+ *     word 1 of the second deciding, at most 65536 attempts); a membrane's
+ *     "side 1" is its label of lower index when the exponent lambda is fixed,
+ *     and a negative lambda takes the value that minimises the correction;
+ *     Baxter's alternative permeation, when chosen, applies to the membranes
+ *     with kappa > 0 (kappa's value is then unused);
  *   - an absorbing membrane (magnetization transfer, end of section 2.1.3)
  *     saturates a walker that meets it with probability P_MT, decided at the
  *     face with a word of its own, independent of the permeation word; the
@@ -132,6 +140,72 @@ double rmso_perm_prob(double kappa, double D1, double D2, double dt) {
     const double den = 1.0 + 0.5 * kappa * (ds1 / D1 + ds2 / D2) * C3;
     const double P = num / den;
     return P > 1.0 ? 1.0 : P;
+}
+
+/* Permeation probabilities across one membrane between side 1 and side 2
+ * with spin concentrations c1, c2 (App. C, general case and the alternative
+ * approach).  model 0: Eq. (gen-perm-prob), P_1->2 = kappa0 ds1/D1 C_d
+ * (c2/c1)^lambda and P_2->1 = kappa0 ds2/D2 C_d (c2/c1)^(lambda-1), with the
+ * input permeability corrected by Eq. (gen-kappa-correction),
+ * kappa = kappa0 / (1 - alpha_lambda), alpha_lambda the mean of the two
+ * probabilities (Eq. gen-kappa-factor-prob); lambda < 0 takes the minimiser
+ * of alpha_lambda, 1 / (1 + c2 sqrt(D2) / (c1 sqrt(D1))).  model 1:
+ * Eq. (alt-perm-prob1-2), probability c_low sqrt(D_low) / (c_high sqrt(D_high))
+ * from the side of larger c sqrt(D) and 1 from the other.  Both clamped to 1. */
+void rmso_conc_perm_probs(double kappa, double D1, double D2, double c1, double c2,
+                          double lambda, int model, double dt, double* P12, double* P21) {
+    const double C3 = 2.0 / 3.0;
+    *P12 = *P21 = 0.0;
+    if (kappa <= 0.0) return;
+    if (model == 1) {
+        const double h1 = c1 * sqrt(D1), h2 = c2 * sqrt(D2);
+        if (h1 >= h2) {
+            *P12 = h2 / h1;
+            *P21 = 1.0;
+        } else {
+            *P12 = 1.0;
+            *P21 = h1 / h2;
+        }
+        return;
+    }
+    const double lam = lambda < 0.0 ? 1.0 / (1.0 + c2 * sqrt(D2) / (c1 * sqrt(D1))) : lambda;
+    const double ds1 = rmso_step_size(D1, dt), ds2 = rmso_step_size(D2, dt);
+    const double r = c2 / c1;
+    const double A = 0.5 * (ds1 / D1 * pow(r, lam) + ds2 / D2 * pow(r, lam - 1.0)) * C3;
+    const double k0 = kappa / (1.0 + kappa * A);
+    const double p12 = k0 * ds1 / D1 * C3 * pow(r, lam);
+    const double p21 = k0 * ds2 / D2 * C3 * pow(r, lam - 1.0);
+    *P12 = p12 > 1.0 ? 1.0 : p12;
+    *P21 = p21 > 1.0 ? 1.0 : p21;
+}
+
+/* Threshold of a probability: a word w < floor(P 2^32) passes. */
+static uint64_t threshold_of(double P) {
+    double t = floor(P * 4294967296.0);
+    if (t > 4294967296.0) t = 4294967296.0;
+    return (uint64_t)t;
+}
+
+/* Permeation thresholds with spin concentrations (rmso_conc_perm_probs for
+ * each pair a < b of labels that are not dead, side 1 = a). */
+int rmso_conc_tables(int n_labels, const double* D, const double* kappa, const uint8_t* dead,
+                     const double* conc, double lambda, int model, double dt, uint64_t* thresh) {
+    if (model != 0 && model != 1) return RMSO_E_INVALID_ARG;
+    if (model == 0 && lambda > 1.0) return RMSO_E_INVALID_ARG;
+    for (int a = 0; a < n_labels; ++a)
+        if (!(dead && dead[a]) && conc && (!(conc[a] > 0.0) || isinf(conc[a])))
+            return RMSO_E_INVALID_ARG;
+    for (int a = 0; a < n_labels; ++a)
+        for (int b = a + 1; b < n_labels; ++b) {
+            if (dead && (dead[a] || dead[b])) continue;
+            const double k = kappa ? kappa[a * n_labels + b] : 0.0;
+            double P12, P21;
+            rmso_conc_perm_probs(k, D[a], D[b], conc ? conc[a] : 1.0, conc ? conc[b] : 1.0,
+                                 lambda, model, dt, &P12, &P21);
+            thresh[a * n_labels + b] = threshold_of(P12);
+            thresh[b * n_labels + a] = threshold_of(P21);
+        }
+    return RMSO_OK;
 }
 
 /* Saturation probability at an absorbing membrane (end of section 2.1.3):
@@ -416,6 +490,7 @@ typedef struct {
     const double* waveform;
     const int64_t* allowed; /* NULL: every voxel allowed */
     int64_t n_allowed;
+    const uint64_t* accept; /* start acceptance threshold per label, or NULL: uniform start */
     /* per-walker results */
     double* w_dx;   /* [n][3] */
     double* w_phi;  /* [n][3*n_shapes] */
@@ -438,11 +513,19 @@ static void walk_one(run_ctx* c, int64_t slot) {
     /* Start (section 2.2, item 1): uniform over the voxels that are not dead,
      * then uniform inside the voxel. */
     uint32_t b0[4], b1[4];
-    philox_block(c->seed, 0u, 2u, wid, b0);
-    philox_block(c->seed, 1u, 2u, wid, b1);
-    const uint64_t r64 = ((uint64_t)b0[1] << 32) | b0[0];
-    const int64_t rank = (int64_t)(((unsigned __int128)r64 * (unsigned __int128)c->n_allowed) >> 64);
-    const int64_t lin = c->allowed ? c->allowed[rank] : rank;
+    int64_t lin = 0;
+    for (uint32_t j = 0;; ++j) {
+        philox_block(c->seed, 2u * j, 2u, wid, b0);
+        philox_block(c->seed, 2u * j + 1u, 2u, wid, b1);
+        const uint64_t r64 = ((uint64_t)b0[1] << 32) | b0[0];
+        const int64_t rank =
+            (int64_t)(((unsigned __int128)r64 * (unsigned __int128)c->n_allowed) >> 64);
+        lin = c->allowed ? c->allowed[rank] : rank;
+        if (!c->accept || j + 1 == 65536u) break;
+        const int64_t vv[3] = {lin % c->g.dims[0], (lin / c->g.dims[0]) % c->g.dims[1],
+                               lin / (c->g.dims[0] * c->g.dims[1])};
+        if ((uint64_t)b1[1] < c->accept[label_at(&c->g, vv)]) break;
+    }
     w.vox[0] = lin % c->g.dims[0];
     w.vox[1] = (lin / c->g.dims[0]) % c->g.dims[1];
     w.vox[2] = lin / (c->g.dims[0] * c->g.dims[1]);
@@ -520,7 +603,8 @@ int rmso_run(const void* labels, int label_bytes, const int64_t dims[3], double 
              const double* dirs, int n_b, const double* bvals, int n_threads, double* signal,
              double* m2, double* m4, double* D_dir, double* K_dir, double* sum_alpha,
              double* b_disc, int64_t counters[3], double* walker_dump, int n_rec,
-             const int64_t* rec_steps, double* rec_out, const double* rho) {
+             const int64_t* rec_steps, double* rec_out, const double* rho, const double* conc,
+             double lambda, int perm_model) {
     if (!labels || (label_bytes != 1 && label_bytes != 2) || !dims || n_walkers < 0 ||
         n_steps < 0 || n_steps > 0xFFFFFFFFLL || n_shapes < 0 || n_shapes > 8 || n_dirs < 0 ||
         n_b < 0 || (n_shapes > 0 && !waveform) || (n_dirs > 0 && !dirs) || n_rec < 0 ||
@@ -543,6 +627,8 @@ int rmso_run(const void* labels, int label_bytes, const int64_t dims[3], double 
     int rc = (sigma && inv_T2 && thresh && kscale && bd) ? RMSO_OK : RMSO_E_OOM;
     if (rc == RMSO_OK)
         rc = rmso_tables(n_labels, D, kappa, T2, dead, dt, voxel_um, sigma, thresh, inv_T2);
+    if (rc == RMSO_OK && (conc || perm_model != 0))
+        rc = rmso_conc_tables(n_labels, D, kappa, dead, conc, lambda, perm_model, dt, thresh);
     uint64_t* thresh_mt = NULL;
     if (rc == RMSO_OK && rho) {
         thresh_mt = malloc(sizeof(uint64_t) * (size_t)n_labels * n_labels);
@@ -567,6 +653,24 @@ int rmso_run(const void* labels, int label_bytes, const int64_t dims[3], double 
             if (rc == RMSO_OK && n_allowed == 0) rc = RMSO_E_INVALID_ARG;
         }
     }
+    /* start density proportional to the spin concentration: a uniform draw
+     * over the allowed voxels is accepted with probability c / max c; the
+     * mean acceptance must be at least 1e-3 */
+    uint64_t* accept = NULL;
+    if (rc == RMSO_OK && conc) {
+        double cmax = 0.0, csum = 0.0;
+        for (int l = 0; l < n_labels; ++l)
+            if (!(dead && dead[l]) && conc[l] > cmax) cmax = conc[l];
+        for (int64_t i = 0; i < nvox; ++i) {
+            const int l = label_bytes == 1 ? ((const uint8_t*)labels)[i] : ((const uint16_t*)labels)[i];
+            if (!(dead && dead[l])) csum += conc[l];
+        }
+        accept = malloc(sizeof(uint64_t) * (size_t)n_labels);
+        if (!accept) rc = RMSO_E_OOM;
+        else if (!(cmax > 0.0) || csum < 1e-3 * cmax * (double)n_allowed) rc = RMSO_E_INVALID_ARG;
+        for (int l = 0; rc == RMSO_OK && l < n_labels; ++l)
+            accept[l] = (dead && dead[l]) ? 0 : threshold_of(conc[l] / cmax);
+    }
     run_ctx* c = calloc(1, sizeof(run_ctx));
     if (!c) rc = RMSO_E_OOM;
     const size_t n = (size_t)n_walkers;
@@ -581,6 +685,7 @@ int rmso_run(const void* labels, int label_bytes, const int64_t dims[3], double 
         c->waveform = waveform;
         c->allowed = allowed;
         c->n_allowed = n_allowed;
+        c->accept = accept;
         c->w_dx = malloc(sizeof(double) * 3 * n + 8);
         c->w_phi = malloc(sizeof(double) * 3 * (size_t)n_shapes * n + 8);
         c->w_R = malloc(sizeof(double) * n + 8);
@@ -749,6 +854,7 @@ int rmso_run(const void* labels, int label_bytes, const int64_t dims[3], double 
         free(c);
     }
     free(allowed);
+    free(accept);
     free(sigma);
     free(inv_T2);
     free(thresh);
