@@ -40,6 +40,10 @@ extern "C" {
 #define RMS_E_BUSY (-8)                /* server: request cannot be admitted now */
 #define RMS_E_TIMEOUT (-9)             /* server: wait timed out */
 
+/* Permeation rules (rms_params.perm_model). */
+#define RMS_PERM_KAPPA 0  /* Eq. (perm-prob-general); with concentrations Eq. (gen-perm-prob) */
+#define RMS_PERM_BAXTER 1 /* Eq. (alt-perm-prob1-2) on the membranes with kappa > 0 */
+
 /* Precision forms of rms_run. */
 #define RMS_FP64 0  /* double-precision walk and reductions */
 #define RMS_MIXED 1 /* int32 voxel + fp32 offset walk, fp64 reductions */
@@ -92,13 +96,33 @@ typedef struct rms_substrate rms_substrate;
  *          independently of the permeation decision, and keeps walking with
  *          weight 0 (Eq. wt-mt; its R becomes INFINITY in walker_dump).  NULL
  *          or all zero: no membrane absorbs.  If every walker is saturated,
- *          sum_alpha is 0 and the normalized results are NaN. */
+ *          sum_alpha is 0 and the normalized results are NaN;
+ *   conc   [n_labels] spin concentration per label, > 0 for every label that is
+ *          not dead, or NULL: all equal (App. C, general case).  Walkers start
+ *          with density proportional to conc (a uniform draw accepted with
+ *          probability c / max c; the mean acceptance over the allowed voxels
+ *          must be at least 1e-3), and with RMS_PERM_KAPPA a membrane between
+ *          labels a < b permeates by Eq. (gen-perm-prob) with side 1 = a and
+ *          the input kappa corrected by Eq. (gen-kappa-correction);
+ *   lambda exponent of Eq. (gen-perm-prob) in [0, 1], or < 0 for the closed
+ *          form 1 / (1 + c_b sqrt(D_b) / (c_a sqrt(D_a))) printed as the
+ *          minimising choice; ignored without conc;
+ *   perm_model  RMS_PERM_KAPPA (kappa's value sets the permeability) or
+ *          RMS_PERM_BAXTER (the membranes with kappa > 0 permeate by Eq.
+ *          (alt-perm-prob1-2): probability c_lo sqrt(D_lo) / (c_hi sqrt(D_hi))
+ *          from the side of larger c sqrt(D), 1 from the other; the limit
+ *          RMS_MAX_PERM_PROB does not apply).
+ * A zero-initialised rms_params apart from n_labels and D gives the plain
+ * model. */
 typedef struct {
     int n_labels;
     const double* D;
     const double* kappa;
     const double* T2;
     const double* rho;
+    const double* conc;
+    double lambda;
+    int perm_model;
 } rms_params;
 
 /* Results of one run.  The caller allocates every array it wants filled and

@@ -22,6 +22,8 @@ LIB_PATH = os.path.join(_HERE, "librms.so")
 RMS_OK = 0
 RMS_FP64 = 0
 RMS_MIXED = 1
+RMS_PERM_KAPPA = 0
+RMS_PERM_BAXTER = 1
 RMS_MAX_SHAPES = 4
 RMS_MAX_SIGNALS = 960
 RMS_MAX_LABELS = 4096
@@ -45,7 +47,8 @@ class RmsError(RuntimeError):
 class _Params(C.Structure):
     _fields_ = [("n_labels", C.c_int), ("D", C.POINTER(C.c_double)),
                 ("kappa", C.POINTER(C.c_double)), ("T2", C.POINTER(C.c_double)),
-                ("rho", C.POINTER(C.c_double))]
+                ("rho", C.POINTER(C.c_double)), ("conc", C.POINTER(C.c_double)),
+                ("lam", C.c_double), ("perm_model", C.c_int)]
 
 
 class _Record(C.Structure):
@@ -230,8 +233,11 @@ def _params(params, keep):
     t2 = None if t2 is None else np.ascontiguousarray(t2, np.float64)
     rho = params.get("rho")
     rho = None if rho is None else np.ascontiguousarray(rho, np.float64).reshape(-1)
-    keep += [Dv, kap, t2, rho]
-    return _Params(Dv.size, _dptr(Dv), _dptr(kap), _dptr(t2), _dptr(rho))
+    conc = params.get("conc")
+    conc = None if conc is None else np.ascontiguousarray(conc, np.float64)
+    keep += [Dv, kap, t2, rho, conc]
+    return _Params(Dv.size, _dptr(Dv), _dptr(kap), _dptr(t2), _dptr(rho), _dptr(conc),
+                   float(params.get("lam", 0.0)), int(params.get("perm_model", RMS_PERM_KAPPA)))
 
 
 class _ResultBuffers:
@@ -267,8 +273,9 @@ def rms_run(sub: Substrate, *, seed, n_walkers, n_steps, dt, waveform=None, dirs
     """Run the walk; returns a dict of numpy results (see ``include/rms.h``).
 
     ``params``: optional dict with ``D``, ``kappa``, ``T2`` overriding the
-    substrate's tissue parameters, and ``rho`` [n, n] making membranes
-    absorbing (magnetization transfer).  ``stream``: a torch.cuda.Stream or a raw
+    substrate's tissue parameters, ``rho`` [n, n] making membranes
+    absorbing (magnetization transfer), and ``conc`` [n], ``lam``,
+    ``perm_model`` for unequal spin concentrations (App. C).  ``stream``: a torch.cuda.Stream or a raw
     hipStream_t (int); None runs on the null stream."""
     lib = _load()
     W, g, b = _protocol(n_steps, waveform, dirs, bvals)

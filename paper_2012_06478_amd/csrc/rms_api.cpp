@@ -47,8 +47,23 @@ namespace {
 // and use P = kappa0 ds1 C / D1 (Eq. perm-prob) with C = C_3 = 2/3; this is
 // Eq. (perm-prob-general).  A membrane word w (uniform on 0..2^32-1)
 // permeates iff w < floor(P 2^32).
+//
+// With spin concentrations c (App. C, general case) a membrane between labels
+// a < b (side 1 = a) uses Eq. (gen-perm-prob): P_a->b = kappa0 ds_a C / D_a r^lam,
+// P_b->a = kappa0 ds_b C / D_b r^(lam-1), r = c_b / c_a, with
+// kappa0 = kappa / (1 + kappa A), A = (ds_a/D_a r^lam + ds_b/D_b r^(lam-1)) C/2
+// (Eq. gen-kappa-correction); lam < 0 takes 1 / (1 + c_b sqrt(D_b) / (c_a
+// sqrt(D_a))).  Baxter's rule (Eq. alt-perm-prob1-2): from the side of larger
+// c sqrt(D) the probability is the ratio of the two, from the other 1; a
+// probability of 1 is applied as 1 - 2^-32 (the largest 32-bit threshold).
+struct PermModel {
+    const double* conc;  // or null: all equal
+    double lambda;
+    int model;           // RMS_PERM_KAPPA or RMS_PERM_BAXTER
+};
+
 int build_tables(const rms_substrate& sub, const double* D, const double* kappa,
-                 const double* T2, double dt, RunSetup& t) {
+                 const double* T2, double dt, const PermModel& pm, RunSetup& t) {
     const int L = sub.n_labels;
     const double C3 = 2.0 / 3.0;
     t.sigma.assign(L, 0.0);
@@ -85,14 +100,35 @@ int build_tables(const rms_substrate& sub, const double* D, const double* kappa,
                 if (k != kappa[static_cast<size_t>(b) * L + a])
                     return fail(RMS_E_INVALID_ARG, "kappa must be symmetric");
                 if (k > 0.0) {
-                    const double k0 = k / (1.0 + 0.5 * k * C3 * (ds[a] / D[a] + ds[b] / D[b]));
-                    const double P = std::min(1.0, k0 * ds[a] * C3 / D[a]);
+                    double P;
+                    if (pm.model == RMS_PERM_BAXTER) {
+                        const double ha = (pm.conc ? pm.conc[a] : 1.0) * std::sqrt(D[a]);
+                        const double hb = (pm.conc ? pm.conc[b] : 1.0) * std::sqrt(D[b]);
+                        P = ha >= hb ? hb / ha : 1.0;
+                    } else if (pm.conc) {
+                        const int s1 = std::min(a, b), s2 = std::max(a, b);
+                        const double c1 = pm.conc[s1], c2 = pm.conc[s2];
+                        const double lam =
+                            pm.lambda < 0.0
+                                ? 1.0 / (1.0 + c2 * std::sqrt(D[s2]) / (c1 * std::sqrt(D[s1])))
+                                : pm.lambda;
+                        const double f12 = std::pow(c2 / c1, lam);
+                        const double f21 = std::pow(c2 / c1, lam - 1.0);
+                        const double A = 0.5 * C3 * (ds[s1] / D[s1] * f12 + ds[s2] / D[s2] * f21);
+                        const double k0 = k / (1.0 + k * A);
+                        P = std::min(1.0, a == s1 ? k0 * ds[s1] * C3 / D[s1] * f12
+                                                  : k0 * ds[s2] * C3 / D[s2] * f21);
+                    } else {
+                        const double k0 = k / (1.0 + 0.5 * k * C3 * (ds[a] / D[a] + ds[b] / D[b]));
+                        P = std::min(1.0, k0 * ds[a] * C3 / D[a]);
+                    }
                     t.max_p = std::max(t.max_p, P);
-                    if (P > RMS_MAX_PERM_PROB)
+                    if (pm.model != RMS_PERM_BAXTER && P > RMS_MAX_PERM_PROB)
                         return fail(RMS_E_PROB_TOO_LARGE,
                                     "permeation probability " + std::to_string(P) +
                                         " > RMS_MAX_PERM_PROB (0.1): lower dt or kappa");
-                    th = static_cast<uint32_t>(std::floor(std::ldexp(P, 32)));
+                    th = P >= 1.0 ? 0xFFFFFFFFu
+                                  : static_cast<uint32_t>(std::floor(std::ldexp(P, 32)));
                 }
             }
             t.thr[static_cast<size_t>(a) * L + b] = th;
@@ -189,14 +225,38 @@ int prepare_run(const rms_substrate* sub, const rms_params* params, uint64_t see
     const double* D = sub->D.data();
     const double* kappa = sub->kappa.empty() ? nullptr : sub->kappa.data();
     const double* T2 = sub->T2.empty() ? nullptr : sub->T2.data();
+    PermModel pm{nullptr, 0.0, RMS_PERM_KAPPA};
     if (params) {
         if (params->n_labels != sub->n_labels || !params->D)
             return fail(RMS_E_INVALID_ARG, "params must give D for every label of the substrate");
         D = params->D;
         kappa = params->kappa;
         T2 = params->T2;
+        pm = PermModel{params->conc, params->lambda, params->perm_model};
+        if (pm.model != RMS_PERM_KAPPA && pm.model != RMS_PERM_BAXTER)
+            return fail(RMS_E_INVALID_ARG, "perm_model must be RMS_PERM_KAPPA or RMS_PERM_BAXTER");
+        if (pm.conc && pm.model == RMS_PERM_KAPPA && !(pm.lambda <= 1.0))
+            return fail(RMS_E_INVALID_ARG, "lambda must be <= 1 (negative: the closed form)");
     }
-    int rc = build_tables(*sub, D, kappa, T2, dt_ms, r);
+    if (pm.conc) {
+        // start density proportional to the concentration (App. C, general case)
+        const int L = sub->n_labels;
+        double cmax = 0.0, csum = 0.0;
+        for (int l = 0; l < L; ++l) {
+            if (sub->dead[l]) continue;
+            if (!(pm.conc[l] > 0.0) || !std::isfinite(pm.conc[l]))
+                return fail(RMS_E_INVALID_ARG, "conc must be finite and > 0 for labels not dead");
+            cmax = std::max(cmax, pm.conc[l]);
+            csum += pm.conc[l] * static_cast<double>(sub->label_count[l]);
+        }
+        if (csum < 1e-3 * cmax * static_cast<double>(sub->n_allowed))
+            return fail(RMS_E_INVALID_ARG, "conc: mean start acceptance below 1e-3");
+        r.accept.assign(L, 0u);
+        for (int l = 0; l < L; ++l)
+            if (!sub->dead[l])
+                r.accept[l] = static_cast<uint64_t>(std::floor(std::ldexp(pm.conc[l] / cmax, 32)));
+    }
+    int rc = build_tables(*sub, D, kappa, T2, dt_ms, pm, r);
     if (rc) return rc;
     if (params && params->rho) {
         rc = build_mt_table(*sub, D, params->rho, dt_ms, r);
@@ -262,7 +322,8 @@ int prepare_run(const rms_substrate* sub, const rms_params* params, uint64_t see
 size_t device_bytes(const RunSetup& r, bool resumable) {
     const size_t L = static_cast<size_t>(r.sub->n_labels);
     size_t b = L * (2 * sizeof(double) + 2 * sizeof(float)) + L * L * sizeof(uint32_t);
-    b += r.thr_mt.size() * sizeof(uint32_t);
+    b += r.thr_mt.size() * sizeof(uint32_t) + r.accept.size() * sizeof(uint64_t);
+    if (!r.accept.empty()) b += static_cast<size_t>(r.n_walkers) * sizeof(uint32_t);
     b += r.gdt.size() * sizeof(double) + 2 * kTrigSize * sizeof(double);
     b += static_cast<size_t>(r.n_walkers) * r.width * sizeof(double);
     b += r.kg.size() * sizeof(double) + r.sig_shape.size() * sizeof(int);
@@ -295,6 +356,9 @@ int DeviceRun::create(const rms_substrate& sub, const RunSetup& r, bool resumabl
     const size_t o_it2_f = take(L * sizeof(float));
     const size_t o_thr = take(L * L * sizeof(uint32_t));
     const size_t o_thr_mt = take(r.thr_mt.size() * sizeof(uint32_t));
+    const size_t o_accept = take(r.accept.size() * sizeof(uint64_t));
+    const size_t o_start_try =
+        take(r.accept.empty() ? 0 : static_cast<size_t>(r.n_walkers) * sizeof(uint32_t));
     const size_t o_gdt = take(r.gdt.size() * sizeof(double));
     const size_t o_trig = take(2 * kTrigSize * sizeof(double));
     const size_t o_wstate = take(static_cast<size_t>(r.n_walkers) * r.width * sizeof(double));
@@ -323,6 +387,9 @@ int DeviceRun::create(const rms_substrate& sub, const RunSetup& r, bool resumabl
     float* d_it2_f = reinterpret_cast<float*>(b + o_it2_f);
     uint32_t* d_thr = reinterpret_cast<uint32_t*>(b + o_thr);
     uint32_t* d_thr_mt = r.thr_mt.empty() ? nullptr : reinterpret_cast<uint32_t*>(b + o_thr_mt);
+    uint64_t* d_accept = r.accept.empty() ? nullptr : reinterpret_cast<uint64_t*>(b + o_accept);
+    uint32_t* d_start_try =
+        r.accept.empty() ? nullptr : reinterpret_cast<uint32_t*>(b + o_start_try);
     double* d_gdt = reinterpret_cast<double*>(b + o_gdt);
     double* d_trig = reinterpret_cast<double*>(b + o_trig);
     double* d_wstate = reinterpret_cast<double*>(b + o_wstate);
@@ -342,6 +409,7 @@ int DeviceRun::create(const rms_substrate& sub, const RunSetup& r, bool resumabl
     RMS_HIP(upload(d_it2_f, r.inv_t2_f, s));
     RMS_HIP(upload(d_thr, r.thr, s));
     if (d_thr_mt) RMS_HIP(upload(d_thr_mt, r.thr_mt, s));
+    if (d_accept) RMS_HIP(upload(d_accept, r.accept, s));
     RMS_HIP(upload(d_gdt, r.gdt, s));
     RMS_HIP(upload(d_trig, r.trig, s));
     RMS_HIP(upload(d_kg, r.kg, s));
@@ -361,6 +429,8 @@ int DeviceRun::create(const rms_substrate& sub, const RunSetup& r, bool resumabl
     div_magic(static_cast<uint32_t>(wp.px), &wp.div_px_m, &wp.div_px_sh);
     div_magic(static_cast<uint32_t>(wp.pxy), &wp.div_pxy_m, &wp.div_pxy_sh);
     wp.allowed = sub.d_allowed;
+    wp.accept = d_accept;
+    wp.start_try = d_start_try;
     wp.n_allowed = sub.n_allowed;
     wp.n_labels = sub.n_labels;
     wp.sigma = d_sigma;
@@ -475,9 +545,11 @@ int rms_create_substrate(const void* labels, int label_bytes, const int64_t dims
     std::vector<uint32_t> allowed;
     bool any_dead = false;
     for (int l = 0; l < n_labels; ++l) any_dead |= sub->dead[l] != 0;
+    sub->label_count.assign(n_labels, 0);
     for (int64_t i = 0; i < nvox; ++i) {
         const int l = label_bytes == 1 ? static_cast<const uint8_t*>(labels)[i]
                                        : static_cast<const uint16_t*>(labels)[i];
+        if (l < n_labels) ++sub->label_count[l];
         if (l >= n_labels) {
             delete sub;
             return fail(RMS_E_LABEL_RANGE, "voxel " + std::to_string(i) + " has label " +
@@ -592,6 +664,7 @@ int rms_run(const rms_substrate* sub, const rms_params* params, uint64_t seed, i
     } eguard{&ev0, &ev1};
     RMS_HIP(hipEventCreate(&ev0));
     RMS_HIP(hipEventCreate(&ev1));
+    RMS_HIP(rms::launch_start_try(dr.wp, stream));
     RMS_HIP(rms::launch_order(dr.wp, stream));
     RMS_HIP(hipEventRecord(ev0, stream));
     RMS_HIP(rms::launch_walk(dr.wp, precision, stream));
@@ -694,6 +767,7 @@ int rms_run_record(const rms_substrate* sub, const rms_params* params, uint64_t 
     } eguard{&ev0, &ev1};
     RMS_HIP(hipEventCreate(&ev0));
     RMS_HIP(hipEventCreate(&ev1));
+    RMS_HIP(rms::launch_start_try(dr.wp, stream));
     RMS_HIP(rms::launch_order(dr.wp, stream));
     RMS_HIP(hipEventRecord(ev0, stream));
     const auto record = [&](int k) {

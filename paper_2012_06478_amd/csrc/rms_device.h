@@ -271,15 +271,23 @@ __device__ __forceinline__ uint32_t entry(const LabelT* __restrict__ lab, uint32
 }
 
 // Start (section 2.2, item 1): uniform over the voxels that are not dead, then
-// uniform inside the voxel.
+// uniform inside the voxel.  With spin concentrations (App. C, general case)
+// the start density is proportional to the voxel's concentration: attempt j
+// draws from substream 2 blocks 2j and 2j + 1 and is kept when word 1 of the
+// second is below the label's acceptance threshold floor(c / max c 2^32); at
+// most kMaxStartTries attempts (the host refuses mean acceptance below 1e-3).
 struct Start {
     int lin;
     uint32_t wox, woy, woz;  // offset words
 };
 
-__device__ __forceinline__ Start draw_start(const WalkPlan& p, const Ids& id) {
-    const uint4 b0 = philox4x32_10(0u, 2u, id.wlo, id.whi, id.k0, id.k1);
-    const uint4 b1 = philox4x32_10(1u, 2u, id.wlo, id.whi, id.k0, id.k1);
+constexpr uint32_t kMaxStartTries = 65536u;
+
+// Attempt j of the start draw; *accept_word is word 1 of its second block.
+__device__ __forceinline__ Start start_attempt(const WalkPlan& p, const Ids& id, uint32_t j,
+                                               uint32_t* accept_word) {
+    const uint4 b0 = philox4x32_10(2u * j, 2u, id.wlo, id.whi, id.k0, id.k1);
+    const uint4 b1 = philox4x32_10(2u * j + 1u, 2u, id.wlo, id.whi, id.k0, id.k1);
     const uint64_t r64 = (static_cast<uint64_t>(b0.y) << 32) | b0.x;
     const uint32_t rank =
         static_cast<uint32_t>(__umul64hi(r64, static_cast<uint64_t>(p.n_allowed)));
@@ -288,7 +296,32 @@ __device__ __forceinline__ Start draw_start(const WalkPlan& p, const Ids& id) {
     s.wox = b0.z;
     s.woy = b0.w;
     s.woz = b1.x;
+    *accept_word = b1.y;
     return s;
+}
+
+// The accepted attempt of a walker's start with spin concentrations (run by a
+// kernel of its own before the walk, which stores it in p.start_try).
+__device__ __forceinline__ uint32_t start_try_of(const WalkPlan& p, const Ids& id) {
+    for (uint32_t j = 0;; ++j) {
+        uint32_t w;
+        const Start s = start_attempt(p, id, j, &w);
+        if (j + 1 == kMaxStartTries) return j;
+        const int e = padded_index(p, s.lin);  // an interior entry: the label, no flags
+        const uint32_t lv = p.label_bytes == 1 ? static_cast<const uint8_t*>(p.labels)[e]
+                                               : static_cast<const uint16_t*>(p.labels)[e];
+        if (static_cast<uint64_t>(w) < p.accept[lv]) return j;
+    }
+}
+
+// The start of walker w (id): the first attempt, or the accepted one found
+// before the walk when the start is weighted by spin concentration.
+__device__ __forceinline__ Start draw_start(const WalkPlan& p, const Ids& id) {
+    uint32_t j = 0u;
+    if (p.start_try)
+        j = p.start_try[(static_cast<uint64_t>(id.whi) << 32) | id.wlo];
+    uint32_t w;
+    return start_attempt(p, id, j, &w);
 }
 
 // ---------------------------------------------------------------------------

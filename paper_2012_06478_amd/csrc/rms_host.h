@@ -25,6 +25,7 @@ struct rms_substrate {
     void* d_labels = nullptr;  // padded volume with halo flags (rms_internal.h)
     uint32_t* d_allowed = nullptr;
     uint32_t n_allowed = 0;
+    std::vector<int64_t> label_count;  // voxels per label
 };
 
 namespace rms {
@@ -60,6 +61,7 @@ struct RunSetup {
     std::vector<float> sigma_f, inv_t2_f;
     std::vector<uint32_t> thr;
     std::vector<uint32_t> thr_mt;  // saturation thresholds (end of section 2.1.3), or empty
+    std::vector<uint64_t> accept;  // start acceptance per label (spin concentrations), or empty
     double max_sigma = 0.0, max_p = 0.0;
     std::vector<double> gdt;
     std::vector<double> trig;  // [kTrigSize][2] angle table (fill_trig_table)

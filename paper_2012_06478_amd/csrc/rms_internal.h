@@ -32,6 +32,10 @@ struct WalkPlan {
     uint32_t div_pxy_m, div_pxy_sh;  // n / pxy, likewise
     const uint32_t* allowed;  // ascending linear indices of non-dead voxels, or null (all)
     uint32_t n_allowed;
+    const uint64_t* accept;   // [n_labels] start acceptance thresholds floor(c / max c 2^32)
+                              // with spin concentrations, or null: uniform start
+    uint32_t* start_try;      // [n_walkers] accepted start attempt of each walker (filled by
+                              // launch_start_try before the walk), or null: attempt 0
     int n_labels;
     const double* sigma;    // [n_labels] step length per label, voxel units
     const double* inv_t2;   // [n_labels] 1/T2 (0 for none)
@@ -126,6 +130,9 @@ size_t seg_state_bytes(int precision, int n_shapes, int64_t n_walkers);
 size_t seg_ctl_bytes(int64_t n_walkers);
 int64_t order_slots(int64_t n_walkers);
 hipError_t launch_order(const WalkPlan& p, hipStream_t s);
+// Accepted start attempt of every walker when the start is weighted by spin
+// concentration (p.accept and p.start_try set); a no-op otherwise.
+hipError_t launch_start_try(const WalkPlan& p, hipStream_t s);
 // Bytes of one resumable walker state.
 size_t walker_state_bytes(int precision, int label_bytes, int n_shapes);
 hipError_t launch_reduce(const ReducePlan& p, hipStream_t s);

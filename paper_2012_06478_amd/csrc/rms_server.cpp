@@ -137,7 +137,8 @@ void rms_server::loop() {
         for (Request* r : admit) {
             int rc = r->dev.create(*r->setup.sub, r->setup, true, stream);
             if (rc == RMS_OK) {
-                const hipError_t eo = rms::launch_order(r->dev.wp, stream);
+                hipError_t eo = rms::launch_start_try(r->dev.wp, stream);
+                if (eo == hipSuccess) eo = rms::launch_order(r->dev.wp, stream);
                 if (eo != hipSuccess) rc = rms::hip_fail("walker order", eo);
             }
             if (rc != RMS_OK) {

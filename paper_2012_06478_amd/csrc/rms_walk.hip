@@ -95,6 +95,16 @@ __global__ __launch_bounds__(kBlock) RMS_WALK_OCCUPANCY void walk_packed_kernel(
     }
 }
 
+// Accepted start attempt per walker (spin concentrations): the rejection loop
+// runs here, once, so the walk kernels only read the attempt index.
+__global__ __launch_bounds__(kBlock) void start_try_kernel(WalkPlan p) {
+    const int64_t w = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+    if (w >= p.n_walkers) return;
+    const Ids id{static_cast<uint32_t>(w), static_cast<uint32_t>(w >> 32),
+                 static_cast<uint32_t>(p.seed), static_cast<uint32_t>(p.seed >> 32)};
+    p.start_try[w] = dev::start_try_of(p, id);
+}
+
 // Step range and flags of every item of a packed launch (a run recorded at
 // several steps walks one interval per launch over the same items).
 __global__ __launch_bounds__(kBlock) void item_range_kernel(PackedItem* items, int n,
@@ -486,6 +496,13 @@ hipError_t launch_walk(const WalkPlan& p, int precision, hipStream_t s) {
     if (precision == RMS_FP64)
         return u8 ? run_ns<dev::WalkerF64, uint8_t>(p, s) : run_ns<dev::WalkerF64, uint16_t>(p, s);
     return u8 ? run_ns<dev::WalkerMixed, uint8_t>(p, s) : run_ns<dev::WalkerMixed, uint16_t>(p, s);
+}
+
+hipError_t launch_start_try(const WalkPlan& p, hipStream_t s) {
+    if (!p.accept || !p.start_try || p.n_walkers <= 0) return hipSuccess;
+    start_try_kernel<<<dim3(static_cast<unsigned>((p.n_walkers + kBlock - 1) / kBlock)), kBlock, 0,
+                       s>>>(p);
+    return hipGetLastError();
 }
 
 hipError_t launch_item_range(PackedItem* items, int n_items, uint32_t step_begin,
