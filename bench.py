@@ -368,6 +368,54 @@ def mt_report(args):
     print(json.dumps(line), flush=True)
 
 
+def conc_report(args):
+    """Unequal spin concentrations (App. C, general case): the workload with
+    the extracellular label at concentration ``--conc`` relative to 1 in the
+    cells (printed closed-form lambda; ``--baxter`` for Baxter's rule on the
+    same membranes), against the same run without; reports both throughputs
+    and the walker share that starts and ends in the cells."""
+    import torch
+    import paper_2012_06478_amd as rms
+    assert torch.cuda.is_available(), "bench needs a GPU"
+    torch.cuda.set_device(0)
+    log(f"[conc] building workload {args.workload}")
+    c = workload(args.workload)
+    prec = rms.RMS_FP64 if args.precision == "fp64" else rms.RMS_MIXED
+    sub = rms.rms_create_substrate(c["labels"], c["voxel_um"], c["D"], c["kappa"], c["T2"],
+                                   c.get("dead"))
+    L = len(c["D"])
+    conc = np.ones(L)
+    conc[0] = args.conc
+    P = dict(D=c["D"], kappa=c["kappa"], T2=c["T2"], conc=conc, lam=-1.0,
+             perm_model=rms.RMS_PERM_BAXTER if args.baxter else rms.RMS_PERM_KAPPA)
+    run = dict(seed=c["seed"], n_walkers=c["n_walkers"], n_steps=c["n_steps"], dt=c["dt"],
+               waveform=c["waveform"], dirs=c["dirs"], bvals=c["bvals"], precision=prec)
+    rms.rms_run(sub, **run)  # warm-up of both paths
+    rms.rms_run(sub, params=P, **run)
+    plain = [rms.rms_run(sub, **run) for _ in range(args.steps)]
+    wc = [rms.rms_run(sub, params=P, **run) for _ in range(args.steps)]
+    d = rms.rms_run(sub, params=P, dump=True, **run)["dump"]
+    sub.close()
+    lab = c["labels"]
+    vin = float(np.sum(lab > 0))
+    want = vin / (vin + args.conc * float(np.sum(lab == 0)))
+    ws = c["n_walkers"] * c["n_steps"]
+    line = {
+        "metric": "walker-steps/s with spin concentrations", "unit": "walker-steps/s",
+        "value": ws / min(r["wall_s"] for r in wc), "higher_is_better": True,
+        "data": "synthetic", "workload": c["name"], "precision": args.precision,
+        "conc_extra": args.conc, "perm_model": "baxter" if args.baxter else "kappa",
+        "plain_walker_steps_per_s": ws / min(r["wall_s"] for r in plain),
+        "kernel_ms_conc": min(r["kernel_ms"] for r in wc),
+        "kernel_ms_plain": min(r["kernel_ms"] for r in plain),
+        "share_in_cells_expected": want,
+        "share_in_cells_start": float(np.mean(d[:, 11] > 0)),
+        "share_in_cells_end": float(np.mean(d[:, 4] > 0)),
+        "permeations": int(wc[0]["n_permeations"]),
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -391,6 +439,11 @@ def main():
     ap.add_argument("--mt", type=float, default=0.0,
                     help="absorbing membranes: surface relaxivity (um/ms) of every cell face; "
                          "reports the run against the plain one")
+    ap.add_argument("--conc", type=float, default=0.0,
+                    help="spin concentration of the extracellular label (cells: 1); reports "
+                         "the run against the plain one")
+    ap.add_argument("--baxter", action="store_true",
+                    help="with --conc: Baxter's permeation rule on the same membranes")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run only a plain 1 GiB device copy (3 times), to scale the "
                          "FETCH_SIZE/WRITE_SIZE counters")
@@ -408,6 +461,9 @@ def main():
         return
     if args.mt > 0:
         mt_report(args)
+        return
+    if args.conc > 0:
+        conc_report(args)
         return
     if args.serve:
         if args.precision == "fp64" and "--precision" not in sys.argv:

@@ -338,7 +338,9 @@ template <typename LabelT, int NS, bool MT>
 struct WalkerF64T {
     static constexpr int kShapes = NS > 0 ? NS : 1;
     static constexpr bool kTrig = true;  // direction from the LDS angle table
-    static constexpr int kWaves = 5;     // waves per SIMD the persistent walk asks for
+    // waves per SIMD the walk kernels ask for: five (96 registers); the
+    // absorbing form holds four more words per step and is given four
+    static constexpr int kWaves = MT ? 4 : 5;
     static constexpr bool kMT = MT;
     uint32_t lb;     // byte offset of the voxel's entry in the padded volume
     int l, l0;       // label, label at the start
@@ -547,7 +549,9 @@ template <typename LabelT, int NS, bool MT>
 struct WalkerMixedT {
     static constexpr int kShapes = NS > 0 ? NS : 1;
     static constexpr bool kTrig = false;  // hardware sine and cosine
-    static constexpr int kWaves = 6;      // waves per SIMD the persistent walk asks for
+    // waves per SIMD the walk kernels ask for: six (80 registers, a small
+    // spill); the absorbing form holds four more words per step and is given five
+    static constexpr int kWaves = MT ? 5 : 6;
     static constexpr bool kMT = MT;
     uint32_t lb;  // byte offset of the voxel's entry in the padded volume
     int l, l0;

@@ -24,7 +24,10 @@ using dev::Ids;
 // which then fits 96 registers (a few bytes of spill outside the step) and
 // runs about 7% faster than at four; six for the mixed walker, which keeps
 // it within 80 registers (left free, it grows past 85 with two waveform
-// shapes and drops to five waves, 16% slower).
+// shapes and drops to five waves, 16% slower).  The absorbing-membrane forms
+// carry four more words per step and ask for one wave fewer: squeezed to the
+// plain forms' counts they reload a spilled value every step (FP64 77.2
+// against 71.5 ms, mixed 62.4 against 59.0 ms on the 200^3 packing).
 #define RMS_WALK_OCCUPANCY __attribute__((amdgpu_waves_per_eu(Walker::kWaves, 8)))
 
 // The angle table of the double-precision direction draw, copied to LDS by
