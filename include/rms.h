@@ -250,6 +250,29 @@ int rms_run_record(const rms_substrate* sub, const rms_params* params, uint64_t 
                    rms_result* out);
 
 /* ---------------------------------------------------------------------------
+ * Post-processing of a run's signals (host only; no device work).
+ * ------------------------------------------------------------------------- */
+
+/* Direction average of the signal for each b value (the spherical mean; the
+ * directions are taken as a uniform sampling of the sphere or, with the
+ * antipodal symmetry of the signal, of a hemisphere).
+ *   signal  [n_b][n_dirs][2] (re, im): one shape of rms_result.signal;
+ *   out     [n_b][2] caller-allocated.
+ * RMS_E_INVALID_ARG for n_b < 1, n_dirs < 1 or a NULL pointer. */
+int rms_spherical_mean(int n_b, int n_dirs, const double* signal, double* out);
+
+/* Cumulant fit of the signal per direction (section 2.3: D and K from the
+ * signal's b dependence, here for any pulse width): least squares of
+ * ln Re S(b) = -b D + b^2 D^2 K / 6 over the b values in (0, b_max] (ln S(0) =
+ * 0 is held exactly).
+ *   bvals  [n_b] ms/um^2; signal [n_b][n_dirs][2] as above;
+ *   D_out, K_out  [n_dirs] caller-allocated (um^2/ms; dimensionless).
+ * RMS_E_INVALID_ARG if fewer than two b values lie in (0, b_max], or a
+ * signal there is not positive. */
+int rms_cumulant_fit(int n_b, const double* bvals, int n_dirs, const double* signal,
+                     double b_max, double* D_out, double* K_out);
+
+/* ---------------------------------------------------------------------------
  * Serving: continuous batching of simulation requests on one GPU.
  *
  * A server keeps the substrates its requests name resident (the caller keeps

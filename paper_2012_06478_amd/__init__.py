@@ -115,6 +115,10 @@ def _load():
                                    C.c_int64, C.c_double, C.c_int, dp, C.c_int, dp, C.c_int, dp,
                                    C.c_int, C.c_void_p, C.POINTER(_Record), C.POINTER(_Result)]
     lib.rms_run_record.restype = C.c_int
+    lib.rms_spherical_mean.argtypes = [C.c_int, C.c_int, dp, dp]
+    lib.rms_spherical_mean.restype = C.c_int
+    lib.rms_cumulant_fit.argtypes = [C.c_int, dp, C.c_int, dp, C.c_double, dp, dp]
+    lib.rms_cumulant_fit.restype = C.c_int
     lib.rms_server_create.argtypes = [C.c_size_t, C.c_int, C.POINTER(C.c_void_p)]
     lib.rms_server_create.restype = C.c_int
     lib.rms_server_submit.argtypes = [C.c_void_p, C.POINTER(_Request), C.POINTER(C.c_int64)]
@@ -135,8 +139,8 @@ def exported_symbols() -> list[str]:
     """Names the library exports through the C ABI (for load checks)."""
     lib = _load()
     names = ["rms_abi_version", "rms_last_error", "rms_create_substrate",
-             "rms_destroy_substrate", "rms_run", "rms_run_record", "rms_server_create",
-             "rms_server_submit",
+             "rms_destroy_substrate", "rms_run", "rms_run_record", "rms_spherical_mean",
+             "rms_cumulant_fit", "rms_server_create", "rms_server_submit",
              "rms_server_poll", "rms_server_wait", "rms_server_stats_get", "rms_server_destroy"]
     return [n for n in names if hasattr(lib, n)]
 
@@ -330,6 +334,38 @@ def rms_run_record(sub: Substrate, *, seed, n_walkers, n_steps, dt, record_steps
     return out
 
 
+def _signal_array(signal):
+    """[n_b, n_dirs] complex -> contiguous [n_b][n_dirs][2] doubles."""
+    S = np.asarray(signal)
+    if S.ndim != 2:
+        raise ValueError("signal must be [n_b, n_dirs] (one shape)")
+    A = np.empty(S.shape + (2,))
+    A[..., 0], A[..., 1] = S.real, S.imag
+    return np.ascontiguousarray(A)
+
+
+def rms_spherical_mean(signal) -> np.ndarray:
+    """Direction average of a [n_b, n_dirs] complex signal; returns [n_b]."""
+    A = _signal_array(signal)
+    out = np.zeros((A.shape[0], 2))
+    _check(_load().rms_spherical_mean(A.shape[0], A.shape[1], _dptr(A), _dptr(out)))
+    return out[:, 0] + 1j * out[:, 1]
+
+
+def rms_cumulant_fit(signal, bvals, b_max: float):
+    """Per direction D and K from ln Re S(b) = -bD + b^2 D^2 K / 6 over
+    0 < b <= b_max; returns (D [n_dirs], K [n_dirs])."""
+    A = _signal_array(signal)
+    b = np.ascontiguousarray(bvals, np.float64)
+    if b.size != A.shape[0]:
+        raise ValueError("bvals must match the signal's b axis")
+    D = np.zeros(A.shape[1])
+    K = np.zeros(A.shape[1])
+    _check(_load().rms_cumulant_fit(b.size, _dptr(b), A.shape[1], _dptr(A), float(b_max),
+                                    _dptr(D), _dptr(K)))
+    return D, K
+
+
 # ------------------------------------------------------------------ server --
 
 def rms_server_create(mem_budget_bytes: int = 0, slice_steps: int = 0):
@@ -376,6 +412,7 @@ def rms_server_destroy(srv) -> None:
 
 
 __all__ = ["rms_abi_version", "rms_last_error", "rms_create_substrate", "rms_destroy_substrate",
-           "rms_run", "rms_run_record", "rms_server_create", "rms_server_submit", "rms_server_poll",
+           "rms_run", "rms_run_record", "rms_spherical_mean", "rms_cumulant_fit",
+           "rms_server_create", "rms_server_submit", "rms_server_poll",
            "rms_server_wait", "rms_server_stats_get", "rms_server_destroy", "Substrate", "RmsError", "RMS_FP64", "RMS_MIXED", "exported_symbols",
            "DUMP_FIELDS"]

@@ -695,6 +695,57 @@ int rms_run(const rms_substrate* sub, const rms_params* params, uint64_t seed, i
     return RMS_OK;
 }
 
+int rms_spherical_mean(int n_b, int n_dirs, const double* signal, double* out) {
+    rms::clear_error();
+    if (n_b < 1 || n_dirs < 1 || !signal || !out)
+        return rms::fail(RMS_E_INVALID_ARG, "spherical mean: n_b, n_dirs >= 1 and arrays required");
+    for (int j = 0; j < n_b; ++j) {
+        double re = 0.0, im = 0.0;
+        for (int d = 0; d < n_dirs; ++d) {
+            re += signal[(static_cast<size_t>(j) * n_dirs + d) * 2];
+            im += signal[(static_cast<size_t>(j) * n_dirs + d) * 2 + 1];
+        }
+        out[2 * j] = re / n_dirs;
+        out[2 * j + 1] = im / n_dirs;
+    }
+    return RMS_OK;
+}
+
+// Per direction: y_j = ln Re S(b_j) = a1 b_j + a2 b_j^2 over 0 < b_j <= b_max,
+// least squares through the origin (the normal equations of the two-column
+// design [b, b^2]); D = -a1 and K = 6 a2 / a1^2.
+int rms_cumulant_fit(int n_b, const double* bvals, int n_dirs, const double* signal,
+                     double b_max, double* D_out, double* K_out) {
+    rms::clear_error();
+    if (n_b < 1 || n_dirs < 1 || !bvals || !signal || !D_out || !K_out)
+        return rms::fail(RMS_E_INVALID_ARG, "cumulant fit: sizes and arrays required");
+    int used = 0;
+    for (int j = 0; j < n_b; ++j) used += bvals[j] > 0.0 && bvals[j] <= b_max;
+    if (used < 2)
+        return rms::fail(RMS_E_INVALID_ARG, "cumulant fit: needs two b values in (0, b_max]");
+    for (int d = 0; d < n_dirs; ++d) {
+        double s11 = 0.0, s12 = 0.0, s22 = 0.0, t1 = 0.0, t2 = 0.0;
+        for (int j = 0; j < n_b; ++j) {
+            const double b = bvals[j];
+            if (!(b > 0.0 && b <= b_max)) continue;
+            const double S = signal[(static_cast<size_t>(j) * n_dirs + d) * 2];
+            if (!(S > 0.0)) return rms::fail(RMS_E_INVALID_ARG, "cumulant fit: signal <= 0");
+            const double y = std::log(S);
+            s11 += b * b;
+            s12 += b * b * b;
+            s22 += b * b * b * b;
+            t1 += b * y;
+            t2 += b * b * y;
+        }
+        const double det = s11 * s22 - s12 * s12;
+        const double a1 = (t1 * s22 - t2 * s12) / det;
+        const double a2 = (s11 * t2 - s12 * t1) / det;
+        D_out[d] = -a1;
+        K_out[d] = 6.0 * a2 / (a1 * a1);
+    }
+    return RMS_OK;
+}
+
 int rms_run_record(const rms_substrate* sub, const rms_params* params, uint64_t seed,
                    int64_t n_walkers, int64_t n_steps, double dt_ms, int n_shapes,
                    const double* waveform, int n_dirs, const double* dirs, int n_b,
