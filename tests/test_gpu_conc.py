@@ -111,3 +111,32 @@ def test_conc_errors():
     finally:
         sub.close()
         tiny.close()
+
+
+def test_conc_forms_agree_bitwise():
+    """rms_run, rms_run_record and the server (each runs the start-attempt
+    kernel before its walk) give identical end results with concentrations,
+    under both permeation rules."""
+    kap = np.array([[0.0, 1.0], [1.0, 0.0]])
+    kw = dict(seed=41, n_walkers=2500, n_steps=600, dt=2e-4, dirs=six_dirs(), bvals=[0.0, 1.0],
+              waveform=np.concatenate([np.ones(150), np.zeros(300), -np.ones(150)]))
+    sub = rms.rms_create_substrate(LAB, 0.1, D, kap)
+    try:
+        for model in (rms.RMS_PERM_KAPPA, rms.RMS_PERM_BAXTER):
+            print(f"[case] conc forms model={model}", flush=True)
+            P = dict(D=D, kappa=kap, conc=CONC, lam=-1.0, perm_model=model)
+            a = rms.rms_run(sub, params=P, **kw)
+            b = rms.rms_run_record(sub, params=P, record_steps=[1, 333, 600], **kw)
+            srv = rms.rms_server_create(0, 200)
+            try:
+                t, shape = rms.rms_server_submit(srv, sub, params=P, **kw)
+                c = rms.rms_server_wait(srv, t, shape)
+            finally:
+                rms.rms_server_destroy(srv)
+            for x in (b, c):
+                for k in ("signal", "m2", "m4", "D", "K"):
+                    assert np.array_equal(a[k], x[k]), k
+                for k in ("sum_alpha", "n_face_events", "n_membrane_hits", "n_permeations"):
+                    assert a[k] == x[k], k
+    finally:
+        sub.close()
