@@ -150,6 +150,47 @@ def test_records_full_size_properties():
     assert np.all(r["D"] > 0) and np.all(r["D"] < Dmax)
 
 
+@pytest.mark.parametrize("precision", [rms.RMS_FP64, rms.RMS_MIXED])
+def test_even_records_match_oracle(precision):
+    """Records every 150 steps (not a multiple of 4: intervals start inside a
+    Philox block) match the oracle's (FP64 to 1e-9, mixed within its bar of
+    the FP64 records) and the end results equal rms_run's."""
+    lab, D, kap, T2 = _cells()
+    steps = [150, 300, 450, 600, 750]
+    kw = dict(seed=17, n_walkers=2000, n_steps=800, dt=2e-4, dirs=six_dirs(), bvals=[0.0, 1.0],
+              waveform=pgse(800, 2e-4, 0.04, 0.08))
+    print(f"[case] even records {steps} precision={precision}", flush=True)
+    sub = rms.rms_create_substrate(lab, 0.1, D, kap, T2)
+    g = rms.rms_run_record(sub, record_steps=steps, precision=precision, **kw)
+    e = rms.rms_run(sub, precision=precision, **kw)
+    gd = rms.rms_run_record(sub, record_steps=steps, **kw)
+    sub.close()
+    _same_end(g, e)
+    if precision == rms.RMS_FP64:
+        o = oracle.run(lab, 0.1, D, kap, T2, None, n_threads=NT, rec_steps=steps, **kw)
+        _assert_records_close(g["records"], o["records"], 1e-9)
+    else:
+        a, b = g["records"], gd["records"]
+        assert np.allclose(a["sum_alpha"], b["sum_alpha"], rtol=1e-6)
+        assert np.max(np.abs(a["m2"] - b["m2"]) / np.max(np.abs(b["m2"]))) < 1e-4
+
+
+def test_records_full_size_uneven():
+    """Records at uneven steps at full size: the end results equal rms_run's bit
+    for bit and sum alpha decreases."""
+    c = configs.ellipsoid_case()
+    steps = [37, 500, 2001, 4444, 7000, 9999]
+    kw = dict(seed=c["seed"], n_walkers=c["n_walkers"], n_steps=c["n_steps"], dt=c["dt"],
+              waveform=c["waveform"], dirs=c["dirs"], bvals=c["bvals"])
+    print("[case] ellipsoids200 full size, uneven records", flush=True)
+    sub = rms.rms_create_substrate(c["labels"], c["voxel_um"], c["D"], c["kappa"], c["T2"])
+    g = rms.rms_run_record(sub, record_steps=steps, **kw)
+    e = rms.rms_run(sub, **kw)
+    sub.close()
+    _same_end(g, e)
+    assert np.all(np.diff(g["records"]["sum_alpha"]) < 0)
+
+
 def test_records_errors():
     """Malformed record lists are refused with RMS_E_INVALID_ARG."""
     sub = rms.rms_create_substrate(cylinder_z(16, 5.0), 0.1, [2.0, 2.0])
