@@ -69,6 +69,20 @@ def kernel_sha() -> str:
     return h.hexdigest()[:16]
 
 
+def walk_kernel_name(fp64: bool, c: dict) -> str:
+    """Name of the walk kernel rms_run launches for workload c: the persistent
+    segmented walk (walk_seg_kernel) for the FP64 form at every size and for
+    the mixed form up to eight rounds of its resident waves (8 x 6 x 1024 x 64
+    walkers); the one-launch walk_kernel for larger mixed runs."""
+    lab = "uint16" if c["labels"].dtype.itemsize == 2 or int(c["labels"].max()) >= 32 else "uint8"
+    ns = int(np.asarray(c["waveform"]).reshape(-1, c["n_steps"]).shape[0])
+    walker = "WalkerF64T" if fp64 else "WalkerMixedT"
+    spec = f"{walker}<{lab},{ns},false>"
+    if fp64 or c["n_walkers"] <= 8 * 6 * 1024 * 64:
+        return f"walk_seg_kernel<{spec}> (persistent)"
+    return f"walk_kernel<{spec}> (one launch)"
+
+
 def traffic_from_profile(name: str, precision: str):
     """HBM bytes per launch of the walk kernel, from the committed rocprofv3
     counter summary, if it was taken on the current kernel source."""
@@ -534,7 +548,7 @@ def main():
         "roofline": {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS,
                      "unit": "TOP/s", "frac": achieved / VALU_PEAK_TOPS,
                      "traffic": traffic_from_profile(c["name"], args.precision),
-                     "kernel": "walk_fp64_kernel" if prec == rms.RMS_FP64 else "walk_mixed_kernel",
+                     "kernel": walk_kernel_name(prec == rms.RMS_FP64, c),
                      "kernel_ms": kernel_s * 1e3, "ops_per_walker_step": OPS_TOTAL},
         "last_signal_b_max_dir0": [float(r["signal"][0, -1, 0].real),
                                    float(r["signal"][0, -1, 0].imag)],
