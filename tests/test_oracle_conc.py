@@ -13,6 +13,11 @@ the alternative permeation of Baxter et al.), CPU only.
 - A walk started with density proportional to c keeps the compartments'
   walker shares at c_i V_i / sum_j c_j V_j after several exchange times,
   with either permeation rule (4 binomial standard errors).
+- The permeation flux at equilibrium, per unit membrane area and unit density
+  of the side it leaves, is the effective permeability kappa' = P D / (ds C3)
+  (Eq. perm-prob read backwards); with Baxter's rule P does not depend on the
+  step, so kappa' scales as dt^(-1/2) (App. C), while under Eq.
+  gen-perm-prob it stays near kappa.
 """
 import math
 import os
@@ -117,3 +122,40 @@ def test_rejects_bad_concentrations(conc):
         oracle.run(cylinder_z(8, 2.0), 0.1, np.array([2.0, 2.0]),
                    np.array([[0.0, 0.1], [0.1, 0.0]]), seed=1, n_walkers=4, n_steps=4,
                    dt=2e-4, conc=np.array(conc))
+
+
+@pytest.mark.parametrize("model,kappa", [(1, 1.0), (0, 2.0)])
+def test_permeation_flux_scaling_with_step(model, kappa):
+    """Two slabs 1 um wide (labels 0 | 1, periodic along x: two membranes of
+    0.4 x 0.4 um), D 2 on both sides, c 1 and 0.3; 20000 walkers started at the
+    concentration equilibrium walk 0.4 ms at dt = 2e-4 and 8e-4 ms.  The
+    permeation count equals sum over sides of kappa'_side N_side / V_side x A x
+    T within 4 Poisson errors plus 0.5%; Baxter's count halves when dt grows
+    four-fold (kappa' ~ dt^(-1/2)), the kappa rule's follows its P/ds."""
+    w, ny, lp = 10, 4, 0.1
+    lab = np.zeros((ny, ny, 2 * w), np.uint8)
+    lab[:, :, w:] = 1
+    D = np.array([2.0, 2.0])
+    conc = np.array([1.0, 0.3])
+    kap = np.array([[0.0, kappa], [kappa, 0.0]])
+    N, T = 20_000, 0.4
+    V = w * lp * (ny * lp) ** 2      # each slab's volume
+    A = 2 * (ny * lp) ** 2           # both membranes
+    got, want = [], []
+    for dt in (2e-4, 8e-4):
+        n = int(round(T / dt))
+        r = oracle.run(lab, lp, D, kap, None, None, seed=11, n_walkers=N, n_steps=n, dt=dt,
+                       dirs=six_dirs(), n_threads=NT, dump=True, conc=conc, perm_model=model)
+        P01, P10 = oracle.conc_perm_probs(kappa, D[0], D[1], conc[0], conc[1], 0.0, model, dt)
+        ds = math.sqrt(6 * D[0] * dt)
+        n0 = int(np.sum(r["dump"][:, 11] == 0))
+        flux = sum(P * D[0] / (ds * C3) * m / V for P, m in ((P01, n0), (P10, N - n0)))
+        e = flux * A * n * dt
+        assert abs(r["n_permeations"] - e) < 4 * math.sqrt(e) + 0.005 * e, (dt, r["n_permeations"], e)
+        got.append(r["n_permeations"])
+        want.append(e)
+    if model == 1:
+        assert math.isclose(want[0] / want[1], 2.0, rel_tol=1e-3)
+    else:
+        assert abs(want[0] / want[1] - 1.0) < 0.1
+    assert abs(got[0] / got[1] - want[0] / want[1]) < 0.03 * want[0] / want[1]
