@@ -337,7 +337,35 @@ def record_report(args):
         "D_dir0": [float(x) for x in rr["D"][:: max(1, steps.size // 10), 0]],
         "K_dir0": [float(x) for x in rr["K"][:: max(1, steps.size // 10), 0]],
     }
+    if c["name"].startswith("axons"):
+        line.update(bundle_report(rms, recd[0], steps * c["dt"], c))
     print(json.dumps(line), flush=True)
+
+
+def bundle_report(rms, r, t, c):
+    """Along and across the axon bundle (its axes run near z): D_par(t) =
+    M2_zz / 2t, D_perp(t) = (M2_xx + M2_yy) / 4t and K_par(t) = M4_zzzz /
+    M2_zz^2 - 3 from the recorded moments (section 2.3); from the end signal
+    of each waveform shape, the direction average over b (the spherical mean)
+    and the cumulant fit of ln S(b) over b <= 1 ms/um^2 for the directions
+    nearest to and farthest from z."""
+    m2, m4 = r["records"]["m2"], r["records"]["m4"]
+    k = max(1, t.size // 10)
+    gz = np.abs(np.asarray(c["dirs"])[:, 2])
+    out = {"bundle_t_ms": [float(x) for x in t[::k]],
+           "D_par": [float(x) for x in (m2[:, 5] / (2 * t))[::k]],
+           "D_perp": [float(x) for x in ((m2[:, 0] + m2[:, 3]) / (4 * t))[::k]],
+           "K_par": [float(x) for x in (m4[:, 14] / m2[:, 5] ** 2 - 3.0)[::k]],
+           "spherical_mean": [], "fit_D_par": [], "fit_K_par": [], "fit_D_perp": [],
+           "fit_K_perp": []}
+    for sig in r["signal"]:
+        out["spherical_mean"].append([float(x.real) for x in rms.rms_spherical_mean(sig)])
+        D, K = rms.rms_cumulant_fit(sig, c["bvals"], 1.0)
+        out["fit_D_par"].append(float(D[np.argmax(gz)]))
+        out["fit_K_par"].append(float(K[np.argmax(gz)]))
+        out["fit_D_perp"].append(float(D[np.argmin(gz)]))
+        out["fit_K_perp"].append(float(K[np.argmin(gz)]))
+    return out
 
 
 def mt_report(args):

@@ -77,3 +77,44 @@ def test_spin_concentrations_full_size_sampled():
     se = math.sqrt(want * (1 - want) / d.shape[0])
     assert abs(np.mean(d[:, 11] > 0) - want) < 4 * se
     assert abs(np.mean(d[:, 4] > 0) - want) < 4 * se * math.sqrt(2)
+
+
+def test_axon_bundle_recorded_moments_and_fits():
+    """The 400 x 400 x 1000 beaded-axon bundle at full size (1e7 walkers x 2e4
+    steps, mixed form) with moments recorded every 1000 steps: the end results
+    equal rms_run's bit for bit; along the bundle (its axes run near z)
+    D_par(t) = M2_zz / 2t exceeds D_perp(t) = (M2_xx + M2_yy) / 4t at every
+    record and stays below the largest D0; D_perp(t) falls with t (restricted
+    inside the axons, hindered outside); with no T2 every record's sum of alpha
+    is the walker count.  From the end signal: the direction average is 1 at
+    b = 0 and falls with b, and the cumulant fit (b <= 1) gives a larger D
+    along the bundle than across it, all positive and not above D0 (within 2%
+    for the fit)."""
+    c = configs.axon_case()
+    prec = rms.RMS_MIXED
+    steps = np.arange(1000, c["n_steps"] + 1, 1000)
+    kw = dict(seed=c["seed"], n_walkers=c["n_walkers"], n_steps=c["n_steps"], dt=c["dt"],
+              waveform=c["waveform"], dirs=c["dirs"], bvals=c["bvals"], precision=prec)
+    print(f"[case] axons full size, {steps.size} records, mixed", flush=True)
+    sub = rms.rms_create_substrate(c["labels"], c["voxel_um"], c["D"], c["kappa"], c["T2"])
+    g = rms.rms_run_record(sub, record_steps=steps, **kw)
+    e = rms.rms_run(sub, **kw)
+    sub.close()
+    for k in ("signal", "m2", "m4", "D", "K"):
+        assert np.array_equal(g[k], e[k]), k
+    r = g["records"]
+    t = steps * c["dt"]
+    assert np.all(r["sum_alpha"] == float(c["n_walkers"]))
+    d_par = r["m2"][:, 5] / (2 * t)
+    d_perp = (r["m2"][:, 0] + r["m2"][:, 3]) / (4 * t)
+    print(f"D_par {d_par[[0, 9, -1]]}, D_perp {d_perp[[0, 9, -1]]}", flush=True)
+    Dmax = float(np.max(c["D"]))
+    assert np.all(d_par > d_perp) and np.all(d_par < Dmax) and np.all(d_perp > 0)
+    assert d_perp[-1] < d_perp[9] < d_perp[0]
+    gz = np.abs(np.asarray(c["dirs"])[:, 2])
+    for sig in g["signal"]:
+        sm = rms.rms_spherical_mean(sig).real
+        assert sm[0] == 1.0 and np.all(np.diff(sm) < 0)
+        D, K = rms.rms_cumulant_fit(sig, c["bvals"], 1.0)
+        assert np.all((D > 0) & (D <= 1.02 * Dmax))
+        assert D[np.argmax(gz)] > D[np.argmin(gz)]
