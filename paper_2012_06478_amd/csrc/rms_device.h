@@ -413,11 +413,13 @@ struct WalkerF64T {
         }
         bool spec = true;  // no reflection yet: rsp holds the entries of the voxels reached
 
-        // path length to axis a's face, divided out only after a permeation
-        const auto face_len = [&](int a) {
+        // gap to axis a's face, and the path length to it (divided out only
+        // after a permeation)
+        const auto face_gap = [&](int a) {
             const double va = pick(v, a), oa = pick(o, a);
-            return (va > 0.0 ? 1.0 - oa : oa) / fabs(va);
+            return va > 0.0 ? 1.0 - oa : oa;
         };
+        const auto face_len = [&](int a) { return face_gap(a) / fabs(pick(v, a)); };
         double P = 0.0, tau = 1.0;
         uint32_t passed = 0, refl = 0;
         uint32_t rawc = 0;  // entry of the voxel last passed into (its halo flags)
@@ -460,12 +462,14 @@ struct WalkerF64T {
                         l = nl;
                         sig = p.sigma[nl];
                         it2 = p.inv_t2[nl];
-                        // the later faces, in order, that lie inside the new budget
+                        // the later faces, in order, that lie inside the new budget:
+                        // face_len < pend compared as gap < pend |v| (no division)
                         const double pend = fma(tau, sig, P);
                         nev = k + 1;
 #pragma unroll
                         for (int j = k + 1; j < 3; ++j)
-                            if (nev == j && face_len(ax[j]) < pend) nev = j + 1;
+                            if (nev == j && face_gap(ax[j]) < pend * fabs(pick(v, ax[j])))
+                                nev = j + 1;
                     }
                 }
                 if (cross) {
@@ -627,11 +631,13 @@ struct WalkerMixedT {
         }
         bool spec = true;  // no reflection yet: rsp holds the entries of the voxels reached
 
-        // path length to axis a's face, divided out only after a permeation
-        const auto face_len = [&](int a) {
+        // gap to axis a's face, and the path length to it (divided out only
+        // after a permeation)
+        const auto face_gap = [&](int a) {
             const float va = pick(v, a), oa = pick(o, a);
-            return (va > 0.0f ? 1.0f - oa : oa) / fabsf(va);
+            return va > 0.0f ? 1.0f - oa : oa;
         };
+        const auto face_len = [&](int a) { return face_gap(a) / fabsf(pick(v, a)); };
         float P = 0.0f, tau = 1.0f;
         uint32_t passed = 0, refl = 0;
         uint32_t rawc = 0;  // entry of the voxel last passed into (its halo flags)
@@ -674,12 +680,14 @@ struct WalkerMixedT {
                         l = nl;
                         sig = p.sigma_f[nl];
                         it2 = p.inv_t2_f[nl];
-                        // the later faces, in order, that lie inside the new budget
+                        // the later faces, in order, that lie inside the new budget:
+                        // face_len < pend compared as gap < pend |v| (no division)
                         const float pend = fmaf(tau, sig, P);
                         nev = k + 1;
 #pragma unroll
                         for (int j = k + 1; j < 3; ++j)
-                            if (nev == j && face_len(ax[j]) < pend) nev = j + 1;
+                            if (nev == j && face_gap(ax[j]) < pend * fabsf(pick(v, ax[j])))
+                                nev = j + 1;
                     }
                 }
                 if (cross) {

@@ -192,7 +192,8 @@ def test_records_full_size_uneven():
 
 
 def test_records_errors():
-    """Malformed record lists are refused with RMS_E_INVALID_ARG."""
+    """Malformed record lists and more than RMS_MAX_RECORDS records are refused
+    with RMS_E_INVALID_ARG; exactly RMS_MAX_RECORDS records (one per step) run."""
     sub = rms.rms_create_substrate(cylinder_z(16, 5.0), 0.1, [2.0, 2.0])
     try:
         for steps in ([], [0], [5, 5], [7, 3], [11]):
@@ -200,5 +201,12 @@ def test_records_errors():
                 rms.rms_run_record(sub, seed=1, n_walkers=10, n_steps=10, dt=2e-4,
                                    record_steps=steps)
             assert ei.value.code == -1, steps
+        with pytest.raises(rms.RmsError) as ei:  # one record more than RMS_MAX_RECORDS
+            rms.rms_run_record(sub, seed=1, n_walkers=10, n_steps=5000, dt=2e-4,
+                               record_steps=list(range(1, 4098)))
+        assert ei.value.code == -1
+        g = rms.rms_run_record(sub, seed=1, n_walkers=64, n_steps=4096, dt=2e-4,
+                               record_steps=list(range(1, 4097)))
+        assert g["records"]["m2"].shape == (4096, 6)
     finally:
         sub.close()
