@@ -71,14 +71,17 @@ def kernel_sha() -> str:
 
 def walk_kernel_name(fp64: bool, c: dict) -> str:
     """Name of the walk kernel rms_run launches for workload c: the persistent
-    segmented walk (walk_seg_kernel) for the FP64 form at every size and for
-    the mixed form up to eight rounds of its resident waves (8 x 6 x 1024 x 64
-    walkers); the one-launch walk_kernel for larger mixed runs."""
+    segmented walk (walk_seg_kernel) when the walkers fill more than one round
+    of resident waves (1024 SIMDs x 5 waves for the FP64 walker, x 6 for the
+    mixed one) and, for the mixed form, at most eight rounds; otherwise the
+    one-launch walk_kernel."""
     lab = "uint16" if c["labels"].dtype.itemsize == 2 or int(c["labels"].max()) >= 32 else "uint8"
     ns = int(np.asarray(c["waveform"]).reshape(-1, c["n_steps"]).shape[0])
     walker = "WalkerF64T" if fp64 else "WalkerMixedT"
     spec = f"{walker}<{lab},{ns},false>"
-    if fp64 or c["n_walkers"] <= 8 * 6 * 1024 * 64:
+    round_walkers = 1024 * (5 if fp64 else 6) * 64
+    n = c["n_walkers"]
+    if n > round_walkers and (fp64 or n <= 8 * round_walkers):
         return f"walk_seg_kernel<{spec}> (persistent)"
     return f"walk_kernel<{spec}> (one launch)"
 

@@ -242,7 +242,7 @@ __global__ __launch_bounds__(kBlock) void order_scatter_kernel(const uint32_t* k
 // every step ends with a partly filled last round of resident waves and a
 // ramp-down while they finish; at 1e6 walkers that is 5-8% of the launch.
 // Here the grid holds only as many blocks as can be resident, and each wave
-// takes work items (64 slots, segment of about n_steps/16 steps) from the
+// takes work items (64 slots, segment of about n_steps/16 steps, 1024 to 4096) from the
 // queue of its XCD (block b serves queue b mod 8, the XCD the walker order
 // gave those slots) in segment-major order, so all walkers advance together
 // and the last partial round is one short segment.  A walker state lives in
@@ -259,7 +259,10 @@ __global__ __launch_bounds__(kBlock) void order_scatter_kernel(const uint32_t* k
 
 constexpr uint32_t kSegPollLimit = 1u << 20;  // polls of 1-2 us: about a second
 constexpr int64_t kSegMinSteps = 1024;
-constexpr int64_t kSegTarget = 16;            // segments per walk, at most
+// At most 4096 steps a segment (about 10 ms at full occupancy), so that a
+// wave never waits anywhere near the poll limit, however long the walk.
+constexpr int64_t kSegMaxSteps = 4096;
+constexpr int64_t kSegTarget = 16;            // segments per walk, at most, up to kSegMaxSteps
 constexpr uint32_t kWave = 64;
 constexpr uint32_t kWavesPerBlock = kBlock / kWave;
 
@@ -268,6 +271,7 @@ static_assert(kSegQueues == kXcds, "one queue per XCD");
 uint32_t seg_steps_of(int64_t n_steps) {
     int64_t s = (n_steps + kSegTarget - 1) / kSegTarget;
     s = (s + 3) / 4 * 4;  // segments start on a block of both Philox streams
+    s = s > kSegMaxSteps ? kSegMaxSteps : s;
     return static_cast<uint32_t>(s < kSegMinSteps ? kSegMinSteps : s);
 }
 
@@ -350,18 +354,33 @@ int seg_grid() {
     return g;
 }
 
+// The persistent walk pays only when the walk needs more than one round of
+// resident waves.  With fewer slot waves than resident ones every item of
+// every segment is handed out at once, and most waves poll for segments of
+// their slots that are still running (a 1e4-walker walk ran 15 times slower
+// than in one launch); such walks take the one-launch kernel, and so do
+// walks so long that the item count (slot waves x segments) would pass 2^30.
 template <template <typename, int> class Walker, typename LabelT, int NS>
 hipError_t run_seg(const WalkPlan& p, hipStream_t s) {
+    const int grid_blocks = seg_grid<Walker<LabelT, NS>, LabelT>();
+    const uint32_t seg_steps = seg_steps_of(p.n_steps);
+    const int64_t n_seg64 = p.n_steps == 0 ? 1 : (p.n_steps + seg_steps - 1) / seg_steps;
+    const int64_t wpq64 = p.n_slots / kWave / kSegQueues;
+    // queue heads, failure word and completion counters start at zero; the
+    // host reads the failure word after either kernel
     const int64_t n_ctl = kSegCtlFixed + p.n_slots / kWave;
     seg_init_kernel<<<dim3(static_cast<unsigned>((n_ctl + kBlock - 1) / kBlock)), kBlock, 0, s>>>(
         p.seg_ctl, n_ctl);
-    const uint32_t seg_steps = seg_steps_of(p.n_steps);
-    const uint32_t n_seg = p.n_steps == 0
-        ? 1u : static_cast<uint32_t>((p.n_steps + seg_steps - 1) / seg_steps);
-    const uint32_t wpq = static_cast<uint32_t>(p.n_slots / kWave / kSegQueues);
+    if (p.n_slots / kWave <= static_cast<int64_t>(grid_blocks) * kWavesPerBlock ||
+        wpq64 * n_seg64 > (int64_t(1) << 30)) {
+        walk_kernel<Walker<LabelT, NS>, LabelT>
+            <<<dim3(static_cast<unsigned>((p.n_slots + kBlock - 1) / kBlock)), kBlock, 0, s>>>(p);
+        return hipGetLastError();
+    }
+    const uint32_t n_seg = static_cast<uint32_t>(n_seg64);
+    const uint32_t wpq = static_cast<uint32_t>(wpq64);
     walk_seg_kernel<Walker<LabelT, NS>, LabelT>
-        <<<dim3(static_cast<unsigned>(seg_grid<Walker<LabelT, NS>, LabelT>())), kBlock, 0, s>>>(
-            p, n_seg, seg_steps, wpq);
+        <<<dim3(static_cast<unsigned>(grid_blocks)), kBlock, 0, s>>>(p, n_seg, seg_steps, wpq);
     return hipGetLastError();
 }
 

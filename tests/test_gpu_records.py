@@ -210,3 +210,21 @@ def test_records_errors():
         assert g["records"]["m2"].shape == (4096, 6)
     finally:
         sub.close()
+
+
+@pytest.mark.parametrize("precision", [rms.RMS_FP64, rms.RMS_MIXED])
+def test_long_walk_persistent_equals_packed(precision):
+    """400000 walkers (more than one round of resident waves: the persistent
+    walk) x 70000 steps (segments capped at 4096 steps: 18 segments): rms_run
+    equals the packed intervals of rms_run_record bit for bit."""
+    lab = cylinder_z(24, 7.0)
+    D, kap = [2.0, 1.7], np.array([[0.0, 0.02], [0.02, 0.0]])
+    kw = dict(seed=12, n_walkers=400_000, n_steps=70_000, dt=2e-4, dirs=six_dirs(),
+              bvals=[0.0, 1.0], waveform=pgse(70_000, 2e-4, 2.0, 10.0), precision=precision)
+    print(f"[case] long walk 4e5 x 7e4 precision={precision}", flush=True)
+    sub = rms.rms_create_substrate(lab, 0.1, D, kap)
+    e = rms.rms_run(sub, **kw)
+    g = rms.rms_run_record(sub, record_steps=[35_001, 70_000], **kw)
+    sub.close()
+    _same_end(g, e)
+    assert g["n_permeations"] > 0
