@@ -449,9 +449,11 @@ size_t order_bytes(int64_t n) {
 
 int64_t order_slots(int64_t n) { return order_used(n) ? kXcds * order_chunk(n) : n; }
 
-// Which ordered runs take the persistent walk.  The fp64 walker holds five
-// waves per SIMD either way, and the persistent walk is faster at every size
-// measured.  The mixed walker keeps six waves in the persistent loop only with
+// Which ordered runs may take the persistent walk (run_seg still takes the
+// one-launch kernel for a walk of at most one round of resident waves).  The
+// fp64 walker holds five waves per SIMD either way, and the persistent walk is
+// faster at every size measured beyond one round.  The mixed walker keeps six
+// waves in the persistent loop only with
 // a small spill: that pays while the tail is a large share of the launch (5%
 // faster at 1e6 walkers, 2.5 rounds of resident waves) but not for long
 // launches (3% slower at 1e7 walkers), so the mixed form takes it up to eight
