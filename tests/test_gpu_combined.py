@@ -1,0 +1,114 @@
+"""The features together: absorbing membranes (end of section 2.1.3), unequal
+spin concentrations with either permeation rule (App. C), T2, a dead label
+(section 2.2, item 1) and both label widths, on the GPU through the C ABI
+against the CPU oracle.
+
+Bars: start labels equal the oracle's for every walker; per walker the end
+state matches for at least 98% of walkers (all of them here), with the same
+saturation decisions, and those to the plain FP64 bars; no walker starts in
+or enters the dead label; rms_run, rms_run_record and the server agree bit
+for bit in both precision forms.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2012_06478_amd as rms
+from rms_inputs import ellipsoid_packing, six_dirs, pgse
+
+pytestmark = pytest.mark.gpu
+
+NT = os.cpu_count() or 4
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _case(dtype):
+    lab, _ = ellipsoid_packing(40, voxel_um=0.1, n_cells=6, semi_um=(0.5, 1.2), seed=4)
+    lab = lab.astype(dtype)
+    L = int(lab.max()) + 1
+    D = np.full(L, 2.0)
+    D[0] = 2.5
+    kap = np.full((L, L), 0.05)
+    np.fill_diagonal(kap, 0.0)
+    T2 = np.full(L, 80.0)
+    T2[0] = 60.0
+    rho = np.zeros((L, L))
+    rho[1:, 0] = 0.1   # cells absorb at their outer faces
+    rho[0, 1:] = 0.05  # and the extracellular side at the same faces
+    conc = np.full(L, 1.0)
+    conc[0] = 0.6
+    dead = np.zeros(L, np.uint8)
+    dead[L - 1] = 1
+    return lab, L, D, kap, T2, rho, conc, dead
+
+
+@pytest.mark.parametrize("dtype", [np.uint8, np.uint16])
+@pytest.mark.parametrize("model", [rms.RMS_PERM_KAPPA, rms.RMS_PERM_BAXTER])
+def test_all_features_per_walker(model, dtype):
+    """2000 walkers x 600 steps, PGSE, 6 directions x 2 b."""
+    lab, L, D, kap, T2, rho, conc, dead = _case(dtype)
+    kw = dict(seed=3, n_walkers=2000, n_steps=600, dt=2e-4, dirs=six_dirs(), bvals=[0.0, 1.0],
+              waveform=pgse(600, 2e-4, 0.03, 0.08))
+    print(f"[case] all features model={model} dtype={np.dtype(dtype).name}", flush=True)
+    sub = rms.rms_create_substrate(lab, 0.1, D, kap, T2, dead)
+    g = rms.rms_run(sub, params=dict(D=D, kappa=kap, T2=T2, rho=rho, conc=conc, lam=-1.0,
+                                     perm_model=model), dump=True, **kw)
+    sub.close()
+    o = oracle.run(lab, 0.1, D, kap, T2, dead, n_threads=NT, dump=True, rho=rho, conc=conc,
+                   lam=-1.0, perm_model=model, **kw)
+    G, O = g["dump"], o["dump"]
+    assert np.array_equal(G[:, 11], O[:, 11])
+    assert not np.any(G[:, 11] == L - 1) and not np.any(G[:, 4] == L - 1)
+    same = np.all(G[:, [4, 5, 6, 7, 11, 12, 13, 14]] == O[:, [4, 5, 6, 7, 11, 12, 13, 14]], axis=1)
+    same &= np.max(np.abs(G[:, 0:3] - O[:, 0:3]), axis=1) <= 1e-9
+    sat_g, sat_o = np.isinf(G[:, 3]), np.isinf(O[:, 3])
+    print(f"walkers identical {same.mean():.4%}, saturated {sat_o.mean():.3f}, "
+          f"permeations {o['n_permeations']}", flush=True)
+    assert same.mean() >= 0.98
+    assert np.array_equal(sat_g[same], sat_o[same])
+    assert sat_o.any() and o["n_permeations"] > 0
+    fin = same & ~sat_o
+    assert np.allclose(G[fin, 3], O[fin, 3], rtol=1e-9, atol=1e-15)
+    assert abs(g["sum_alpha"] - o["sum_alpha"]) <= 0.02 * o["sum_alpha"]
+
+
+@pytest.mark.parametrize("precision", [rms.RMS_FP64, rms.RMS_MIXED])
+def test_all_features_forms_agree_bitwise(precision):
+    """The same case (u16, Baxter's rule) as one launch, as packed intervals
+    with records and through the server beside a plain request."""
+    lab, L, D, kap, T2, rho, conc, dead = _case(np.uint16)
+    P = dict(D=D, kappa=kap, T2=T2, rho=rho, conc=conc, lam=-1.0, perm_model=rms.RMS_PERM_BAXTER)
+    kw = dict(seed=8, n_walkers=3000, n_steps=700, dt=2e-4, dirs=six_dirs(), bvals=[0.0, 1.0],
+              waveform=pgse(700, 2e-4, 0.03, 0.08), precision=precision)
+    print(f"[case] all features forms precision={precision}", flush=True)
+    sub = rms.rms_create_substrate(lab, 0.1, D, kap, T2, dead)
+    try:
+        a = rms.rms_run(sub, params=P, **kw)
+        b = rms.rms_run_record(sub, params=P, record_steps=[5, 351, 700], **kw)
+        srv = rms.rms_server_create(0, 128)
+        try:
+            t1, s1 = rms.rms_server_submit(srv, sub, params=P, **kw)
+            t2, s2 = rms.rms_server_submit(srv, sub, **kw)
+            c = rms.rms_server_wait(srv, t1, s1)
+            d = rms.rms_server_wait(srv, t2, s2)
+        finally:
+            rms.rms_server_destroy(srv)
+        plain = rms.rms_run(sub, **kw)
+    finally:
+        sub.close()
+    for x in (b, c):
+        for k in ("signal", "m2", "m4", "D", "K"):
+            assert np.array_equal(a[k], x[k]), k
+        for k in ("sum_alpha", "n_face_events", "n_membrane_hits", "n_permeations"):
+            assert a[k] == x[k], k
+    for k in ("signal", "m2", "sum_alpha"):
+        assert np.array_equal(np.asarray(d[k]), np.asarray(plain[k])), k
+    assert a["sum_alpha"] < plain["sum_alpha"]
