@@ -177,6 +177,41 @@ def test_four_shapes_and_anisotropic_volume():
     _assert_summary(g, o, 1e-9)
 
 
+def test_maximum_labels_and_signals():
+    """RMS_MAX_LABELS labels and RMS_MAX_SIGNALS signals: a 64^3 u16 volume of
+    4096 cubes of 4^3 voxels (labels 0..4095), D from 1.5 to 2.5 by label,
+    every pair permeable (kappa 0.05); 4 shapes x 8 b x 30 directions = 960
+    signals; 512 walkers x 300 steps against the oracle per walker and in
+    summary.  One label or one signal more is refused with RMS_E_INVALID_ARG."""
+    assert rms.RMS_MAX_LABELS == 4096 and rms.RMS_MAX_SIGNALS == 960
+    i = np.arange(64) // 4
+    lab = (i[:, None, None] * 256 + i[None, :, None] * 16 + i[None, None, :]).astype(np.uint16)
+    L = 4096
+    D = 1.5 + np.arange(L) / (L - 1)
+    kap = np.full((L, L), 0.05)
+    np.fill_diagonal(kap, 0.0)
+    n, dt = 300, 2e-4
+    wf = np.stack([pgse(n, dt, 0.004 * k, 0.01 * k) for k in (1, 2, 3, 4)])
+    bvals = [0.0, 0.1, 0.2, 0.5, 1.0, 1.5, 2.0, 3.0]
+    dirs = fibonacci_hemisphere(30)
+    g, o = _both(lab, 0.1, D, kap, None, seed=21, n_walkers=512, n_steps=n, dt=dt, waveform=wf,
+                 dirs=dirs, bvals=bvals)
+    assert g["signal"].shape == (4, 8, 30) and o["n_permeations"] > 0
+    _assert_walkers(g, o, 1e-9)
+    _assert_summary(g, o, 1e-9)
+    with pytest.raises(rms.RmsError) as ei:
+        rms.rms_create_substrate(np.full((2, 2, 2), 4096, np.uint16), 0.1, np.full(L + 1, 2.0))
+    assert ei.value.code == -1
+    sub = rms.rms_create_substrate(lab, 0.1, D, kap)
+    try:
+        with pytest.raises(rms.RmsError) as ei:
+            rms.rms_run(sub, seed=1, n_walkers=64, n_steps=n, dt=dt, waveform=wf,
+                        dirs=fibonacci_hemisphere(31), bvals=bvals)
+        assert ei.value.code == -1
+    finally:
+        sub.close()
+
+
 def test_ellipsoid_config_full_size_sampled():
     """The 200^3 u16 permeable packing at its full size (1e6 walkers x 1e4
     steps, 30 directions x 6 b), in the launch configuration the benchmark
