@@ -36,7 +36,9 @@ extern "C" {
 #define RMS_E_PROB_TOO_LARGE (-4)      /* a permeation probability > RMS_MAX_PERM_PROB */
 #define RMS_E_UNBALANCED_WAVEFORM (-5) /* |sum_i G_i| > 1e-9 sum_i |G_i| for a shape */
 #define RMS_E_OOM (-6)                 /* device or host allocation failed */
-#define RMS_E_DEVICE (-7)              /* a HIP runtime call failed */
+#define RMS_E_DEVICE (-7)              /* a HIP runtime call failed, or a wave of the
+                                          persistent walk gave up a bounded wait for
+                                          an earlier segment (no result) */
 #define RMS_E_BUSY (-8)                /* server: request cannot be admitted now */
 #define RMS_E_TIMEOUT (-9)             /* server: wait timed out */
 
