@@ -783,69 +783,146 @@ int rms_run_record(const rms_substrate* sub, const rms_params* params, uint64_t 
     rc = dr.create(*sub, r, true, stream);
     if (rc) return rc;
 
-    // the walk plan, one packed item per block of thread slots (their step
-    // range is set on the device before each interval) and the reduced values
-    // of each record (the layout of ReducePlan::result without signals)
+    // Two walk plans that differ only in the buffer the walker records go to,
+    // the items of the two halves of the thread slots for each plan (one item
+    // per block; their step range is set on the device before each interval),
+    // and the reduced values of each record (the layout of ReducePlan::result
+    // without signals).  The halves walk on two streams and the records of
+    // consecutive intervals alternate between the two buffers, so one half's
+    // next interval fills the partly idle last round of waves of the other
+    // half's, and a record is reduced while the walk goes on.  The result is
+    // the same: each walker's steps and each reduction are unchanged.
     const int64_t n_items64 = (dr.wp.n_slots + rms::kBlock - 1) / rms::kBlock;
     if (n_items64 > INT32_MAX) return fail(RMS_E_INVALID_ARG, "too many walkers");
     const int n_items = static_cast<int>(n_items64);
+    // half A is a multiple of 8 blocks, so every block keeps the XCD (block
+    // index mod 8) its walkers were ordered for
+    const int h_a = n_items >= 16 ? n_items / 2 / 8 * 8 : n_items;
+    const int h_b = n_items - h_a;
     const int rec_stride = rms::kAccFixed + 2 * n_dirs;
-    const size_t o_items = (sizeof(rms::WalkPlan) + 255) / 256 * 256;
-    const size_t o_rec = o_items + (static_cast<size_t>(n_items) * sizeof(rms::PackedItem) + 255) /
-                                       256 * 256;
-    const size_t extra = o_rec + static_cast<size_t>(n_rec) * rec_stride * sizeof(double);
+    const size_t items_b = (static_cast<size_t>(n_items) * sizeof(rms::PackedItem) + 255) / 256 * 256;
+    const size_t wst_b = (static_cast<size_t>(n_walkers) * r.width * sizeof(double) + 255) / 256 * 256;
+    const size_t o_items = (2 * sizeof(rms::WalkPlan) + 255) / 256 * 256;  // plans[2], an array
+    const size_t o_rec = o_items + 2 * items_b;
+    const size_t o_wst = o_rec + (static_cast<size_t>(n_rec) * rec_stride * sizeof(double) + 255) /
+                                     256 * 256;
+    const size_t extra = o_wst + wst_b;
     void* xb = nullptr;
     RMS_HIP(hipMallocAsync(&xb, extra, stream));
     dr.ptrs.push_back(xb);
-    auto* d_plan = static_cast<rms::WalkPlan*>(xb);
-    auto* d_items = reinterpret_cast<rms::PackedItem*>(static_cast<uint8_t*>(xb) + o_items);
-    auto* d_rec = reinterpret_cast<double*>(static_cast<uint8_t*>(xb) + o_rec);
-    std::vector<rms::PackedItem> items(static_cast<size_t>(n_items));
-    for (int i = 0; i < n_items; ++i)
-        items[i] = rms::PackedItem{static_cast<int64_t>(i) * rms::kBlock, 0, 0u, 0u, 0u};
-    RMS_HIP(hipMemcpyAsync(d_plan, &dr.wp, sizeof(rms::WalkPlan), hipMemcpyHostToDevice, stream));
-    RMS_HIP(hipMemcpyAsync(d_items, items.data(), items.size() * sizeof(rms::PackedItem),
-                           hipMemcpyHostToDevice, stream));
+    uint8_t* xbase = static_cast<uint8_t*>(xb);
+    auto* d_plan = reinterpret_cast<rms::WalkPlan*>(xbase);
+    auto* d_rec = reinterpret_cast<double*>(xbase + o_rec);
+    double* wst[2] = {dr.wp.wstate, reinterpret_cast<double*>(xbase + o_wst)};
+    rms::PackedItem* d_items[2] = {reinterpret_cast<rms::PackedItem*>(xbase + o_items),
+                                   reinterpret_cast<rms::PackedItem*>(xbase + o_items + items_b)};
+    rms::WalkPlan plans[2] = {dr.wp, dr.wp};
+    plans[1].wstate = wst[1];
+    RMS_HIP(hipMemcpyAsync(d_plan, plans, sizeof(plans), hipMemcpyHostToDevice, stream));
+    // host staging must outlive the asynchronous copies: keep both item lists
+    std::vector<rms::PackedItem> items(2 * static_cast<size_t>(n_items));
+    for (int q = 0; q < 2; ++q) {
+        for (int i = 0; i < n_items; ++i)
+            items[static_cast<size_t>(q) * n_items + i] =
+                rms::PackedItem{static_cast<int64_t>(i) * rms::kBlock, q, 0u, 0u, 0u};
+        RMS_HIP(hipMemcpyAsync(d_items[q], items.data() + static_cast<size_t>(q) * n_items,
+                               static_cast<size_t>(n_items) * sizeof(rms::PackedItem),
+                               hipMemcpyHostToDevice, stream));
+    }
 
-    hipEvent_t ev0 = nullptr, ev1 = nullptr;
-    struct EventGuard {
-        hipEvent_t* a;
-        hipEvent_t* b;
-        ~EventGuard() {
-            if (*a) hipEventDestroy(*a);
-            if (*b) hipEventDestroy(*b);
+    // events and the second stream; on every exit the first stream waits for
+    // the second before the run's memory is released
+    std::vector<hipEvent_t> events;
+    hipStream_t sb = nullptr;
+    struct StreamGuard {
+        hipStream_t a;
+        hipStream_t* b;
+        std::vector<hipEvent_t>* ev;
+        ~StreamGuard() {
+            if (*b) {
+                hipEvent_t e = nullptr;
+                if (hipEventCreateWithFlags(&e, hipEventDisableTiming) == hipSuccess) {
+                    hipEventRecord(e, *b);
+                    hipStreamWaitEvent(a, e, 0);
+                    hipEventDestroy(e);
+                }
+                hipStreamDestroy(*b);
+            }
+            for (hipEvent_t e : *ev) hipEventDestroy(e);
         }
-    } eguard{&ev0, &ev1};
-    RMS_HIP(hipEventCreate(&ev0));
-    RMS_HIP(hipEventCreate(&ev1));
+    } sguard{stream, &sb, &events};
+    const auto new_event = [&](bool timing, hipEvent_t* e) -> hipError_t {
+        *e = nullptr;
+        const hipError_t err = timing ? hipEventCreate(e)
+                                      : hipEventCreateWithFlags(e, hipEventDisableTiming);
+        if (err == hipSuccess) events.push_back(*e);
+        return err;
+    };
+    hipEvent_t ev0 = nullptr, ev1 = nullptr, ev_setup = nullptr;
+    RMS_HIP(new_event(true, &ev0));
+    RMS_HIP(new_event(true, &ev1));
+    RMS_HIP(new_event(false, &ev_setup));
+    if (h_b > 0) RMS_HIP(hipStreamCreateWithFlags(&sb, hipStreamNonBlocking));
     RMS_HIP(rms::launch_start_try(dr.wp, stream));
     RMS_HIP(rms::launch_order(dr.wp, stream));
     RMS_HIP(hipEventRecord(ev0, stream));
-    const auto record = [&](int k) {
-        rms::ReducePlan rr = dr.rp;
-        rr.n_shapes = 0;
-        rr.n_sig = 0;
-        rr.n_acc = rms::kAccFixed;
-        rr.t_ms = static_cast<double>(rec->steps[k]) * r.dt;
-        rr.result = d_rec + static_cast<size_t>(k) * rec_stride;
-        return rms::launch_reduce(rr, stream);
-    };
+    if (sb) {
+        RMS_HIP(hipEventRecord(ev_setup, stream));
+        RMS_HIP(hipStreamWaitEvent(sb, ev_setup, 0));
+    }
+    std::vector<hipEvent_t> ev_b(static_cast<size_t>(n_rec) + 1, nullptr);
+    std::vector<hipEvent_t> ev_r(static_cast<size_t>(n_rec), nullptr);
+    const bool mt = !r.thr_mt.empty();
+    int last_q = 0;
     int64_t b = 0;
     for (int k = 0; k <= n_rec; ++k) {
         const int64_t e = k < n_rec ? rec->steps[k] : n_steps;
-        if (e > b) {  // one launch per interval; an intermediate end writes the records
-            RMS_HIP(rms::launch_item_range(d_items, n_items, static_cast<uint32_t>(b),
-                                           static_cast<uint32_t>(e),
-                                           e < n_steps ? rms::kItemRecord : 0u, stream));
-            RMS_HIP(rms::launch_walk_packed(d_items, n_items, d_plan, precision,
-                                            sub->dev_label_bytes, r.n_shapes, !r.thr_mt.empty(),
-                                            stream));
+        const int q = k % 2;  // record buffer of this interval
+        if (e > b) {  // one launch per half and interval; an intermediate end writes the records
+            const uint32_t flags = e < n_steps ? rms::kItemRecord : 0u;
+            RMS_HIP(rms::launch_item_range(d_items[q], h_a, static_cast<uint32_t>(b),
+                                           static_cast<uint32_t>(e), flags, stream));
+            RMS_HIP(rms::launch_walk_packed(d_items[q], h_a, d_plan, precision,
+                                            sub->dev_label_bytes, r.n_shapes, mt, stream));
+            if (sb) {
+                // buffer q was last read by the reduction of record k - 2
+                if (k >= 2 && ev_r[k - 2]) RMS_HIP(hipStreamWaitEvent(sb, ev_r[k - 2], 0));
+                RMS_HIP(rms::launch_item_range(d_items[q] + h_a, h_b, static_cast<uint32_t>(b),
+                                               static_cast<uint32_t>(e), flags, sb));
+                RMS_HIP(rms::launch_walk_packed(d_items[q] + h_a, h_b, d_plan, precision,
+                                                sub->dev_label_bytes, r.n_shapes, mt, sb));
+                RMS_HIP(new_event(false, &ev_b[k]));
+                RMS_HIP(hipEventRecord(ev_b[k], sb));
+            }
+            last_q = q;
             b = e;
         }
-        if (k < n_rec) RMS_HIP(record(k));
+        if (k < n_rec) {
+            if (sb && ev_b[k]) RMS_HIP(hipStreamWaitEvent(stream, ev_b[k], 0));
+            rms::ReducePlan rr = dr.rp;
+            rr.wstate = wst[q];
+            rr.n_shapes = 0;
+            rr.n_sig = 0;
+            rr.n_acc = rms::kAccFixed;
+            rr.t_ms = static_cast<double>(rec->steps[k]) * r.dt;
+            rr.result = d_rec + static_cast<size_t>(k) * rec_stride;
+            RMS_HIP(rms::launch_reduce(rr, stream));
+            if (sb) {
+                RMS_HIP(new_event(false, &ev_r[k]));
+                RMS_HIP(hipEventRecord(ev_r[k], stream));
+            }
+        }
+    }
+    if (sb) {  // the second stream's last interval
+        hipEvent_t ev_end = nullptr;
+        RMS_HIP(new_event(false, &ev_end));
+        RMS_HIP(hipEventRecord(ev_end, sb));
+        RMS_HIP(hipStreamWaitEvent(stream, ev_end, 0));
     }
     RMS_HIP(hipEventRecord(ev1, stream));
-    RMS_HIP(rms::launch_reduce(dr.rp, stream));
+    rms::ReducePlan rfin = dr.rp;
+    rfin.wstate = wst[last_q];
+    RMS_HIP(rms::launch_reduce(rfin, stream));
 
     std::vector<double> res(r.n_res), recv(static_cast<size_t>(n_rec) * rec_stride);
     RMS_HIP(hipMemcpyAsync(res.data(), dr.rp.result, r.n_res * sizeof(double),
@@ -853,7 +930,7 @@ int rms_run_record(const rms_substrate* sub, const rms_params* params, uint64_t 
     RMS_HIP(hipMemcpyAsync(recv.data(), d_rec, recv.size() * sizeof(double),
                            hipMemcpyDeviceToHost, stream));
     if (out->walker_dump)
-        RMS_HIP(hipMemcpyAsync(out->walker_dump, dr.wp.wstate,
+        RMS_HIP(hipMemcpyAsync(out->walker_dump, wst[last_q],
                                static_cast<size_t>(n_walkers) * r.width * sizeof(double),
                                hipMemcpyDeviceToHost, stream));
     RMS_HIP(hipStreamSynchronize(stream));
