@@ -239,12 +239,14 @@ typedef struct {
 /* rms_run with the displacement moments recorded at rec->steps.  Every other
  * argument and every field of `out` is as for rms_run, and the end results
  * equal rms_run's bit for bit (a walker's trajectory depends only on seed,
- * walker and step).  The walk runs as one launch per interval between record
+ * walker and step).  The walk runs interval by interval between record
  * steps, keeping the walker states in device memory (120 extra bytes per
- * walker in FP64, 100 in the mixed form, with one waveform shape);
- * out->kernel_ms covers the walk launches and the record reductions between
- * them.  Errors as rms_run, and RMS_E_INVALID_ARG for a malformed record
- * list. */
+ * walker in FP64, 100 in the mixed form, with one waveform shape) and a
+ * second buffer of walker records (8 (15 + 3 n_shapes) bytes per walker); half
+ * of the walkers walk on hip_stream and half on a non-blocking stream the call
+ * creates, waits for and destroys before it returns.  out->kernel_ms covers
+ * the walk launches and the record reductions between them.  Errors as
+ * rms_run, and RMS_E_INVALID_ARG for a malformed record list. */
 int rms_run_record(const rms_substrate* sub, const rms_params* params, uint64_t seed,
                    int64_t n_walkers, int64_t n_steps, double dt_ms, int n_shapes,
                    const double* waveform, int n_dirs, const double* dirs, int n_b,
