@@ -71,17 +71,15 @@ def kernel_sha() -> str:
 
 def walk_kernel_name(fp64: bool, c: dict) -> str:
     """Name of the walk kernel rms_run launches for workload c: the persistent
-    segmented walk (walk_seg_kernel) when the walkers fill more than one round
-    of resident waves (1024 SIMDs x 5 waves for the FP64 walker, x 6 for the
-    mixed one) and, for the mixed form, at most eight rounds; otherwise the
-    one-launch walk_kernel."""
+    segmented walk (walk_seg_kernel) when the walkers fill between 1.5 and 4.5
+    rounds of resident waves (1024 SIMDs x 5 waves for the FP64 walker, x 6
+    for the mixed one), else the one-launch walk_kernel."""
     lab = "uint16" if c["labels"].dtype.itemsize == 2 or int(c["labels"].max()) >= 32 else "uint8"
     ns = int(np.asarray(c["waveform"]).reshape(-1, c["n_steps"]).shape[0])
     walker = "WalkerF64T" if fp64 else "WalkerMixedT"
     spec = f"{walker}<{lab},{ns},false>"
-    round_walkers = 1024 * (5 if fp64 else 6) * 64
-    n = c["n_walkers"]
-    if n > round_walkers and (fp64 or n <= 8 * round_walkers):
+    rounds = c["n_walkers"] / (1024 * (5 if fp64 else 6) * 64)
+    if 1.5 < rounds <= 4.5:
         return f"walk_seg_kernel<{spec}> (persistent)"
     return f"walk_kernel<{spec}> (one launch)"
 
@@ -468,6 +466,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--precision", choices=("fp64", "mixed"), default="fp64")
     ap.add_argument("--workload", choices=WORKLOADS, default="ellipsoids200")
+    ap.add_argument("--walkers", type=int, default=0,
+                    help="walker count in place of the workload's (the plain benchmark only)")
     ap.add_argument("--cpu-sample-walkers", type=int, default=250_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--precision-report", action="store_true",
@@ -532,6 +532,9 @@ def main():
         return
     log(f"[bench] building workload {args.workload}")
     c = workload(args.workload)
+    default_walkers = c["n_walkers"]
+    if args.walkers:
+        c["n_walkers"] = args.walkers
     prec = rms.RMS_FP64 if args.precision == "fp64" else rms.RMS_MIXED
     t0 = time.perf_counter()
     sub = rms.rms_create_substrate(c["labels"], c["voxel_um"], c["D"], c["kappa"], c["T2"],
@@ -578,7 +581,8 @@ def main():
                    "precision": args.precision},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS,
                      "unit": "TOP/s", "frac": achieved / VALU_PEAK_TOPS,
-                     "traffic": traffic_from_profile(c["name"], args.precision),
+                     "traffic": (traffic_from_profile(c["name"], args.precision)
+                                 if c["n_walkers"] == default_walkers else None),
                      "kernel": walk_kernel_name(prec == rms.RMS_FP64, c),
                      "kernel_ms": kernel_s * 1e3, "ops_per_walker_step": OPS_TOTAL},
         "last_signal_b_max_dir0": [float(r["signal"][0, -1, 0].real),

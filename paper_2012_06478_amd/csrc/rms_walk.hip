@@ -354,25 +354,32 @@ int seg_grid() {
     return g;
 }
 
-// The persistent walk pays only when the walk needs more than one round of
-// resident waves.  With fewer slot waves than resident ones every item of
-// every segment is handed out at once, and most waves poll for segments of
-// their slots that are still running (a 1e4-walker walk ran 15 times slower
-// than in one launch); such walks take the one-launch kernel, and so do
-// walks so long that the item count (slot waves x segments) would pass 2^30.
+// The persistent walk pays only where a one-launch walk loses much of its
+// time to the partly filled last round of waves: between 1.5 and 4.5 rounds
+// of resident waves (measured at 200^3, kernel ms one launch / persistent:
+// FP64 0.7e6 walkers 48.1 / 45.7, 1e6 66.6 / 64.7, 2e6 120.3 / 123.7, 1e7
+// 555.7 / 595.6; mixed 0.7e6 40.8 / 38.3, 1e6 56.6 / 53.7, 3e6 144.7 /
+// 151.0).  Just above one round every item of the first segments is handed
+// out at once and many waves poll for segments of their slots still running
+// (0.4e6 walkers: FP64 33.7 / 48.2, mixed 31.0 / 82.6), and below one round
+// all of them do.  Other walks, and walks so long that the item count (slot
+// waves x segments) would pass 2^30, take the one-launch kernel.
 template <template <typename, int> class Walker, typename LabelT, int NS>
 hipError_t run_seg(const WalkPlan& p, hipStream_t s) {
     const int grid_blocks = seg_grid<Walker<LabelT, NS>, LabelT>();
     const uint32_t seg_steps = seg_steps_of(p.n_steps);
     const int64_t n_seg64 = p.n_steps == 0 ? 1 : (p.n_steps + seg_steps - 1) / seg_steps;
     const int64_t wpq64 = p.n_slots / kWave / kSegQueues;
+    const int64_t slot_waves = p.n_slots / kWave;
+    const int64_t resident = static_cast<int64_t>(grid_blocks) * kWavesPerBlock;
+    const bool persistent = 2 * slot_waves > 3 * resident && 2 * slot_waves <= 9 * resident &&
+                            wpq64 * n_seg64 <= (int64_t(1) << 30);
     // queue heads, failure word and completion counters start at zero; the
     // host reads the failure word after either kernel
     const int64_t n_ctl = kSegCtlFixed + p.n_slots / kWave;
     seg_init_kernel<<<dim3(static_cast<unsigned>((n_ctl + kBlock - 1) / kBlock)), kBlock, 0, s>>>(
         p.seg_ctl, n_ctl);
-    if (p.n_slots / kWave <= static_cast<int64_t>(grid_blocks) * kWavesPerBlock ||
-        wpq64 * n_seg64 > (int64_t(1) << 30)) {
+    if (!persistent) {
         walk_kernel<Walker<LabelT, NS>, LabelT>
             <<<dim3(static_cast<unsigned>((p.n_slots + kBlock - 1) / kBlock)), kBlock, 0, s>>>(p);
         return hipGetLastError();
@@ -449,19 +456,17 @@ size_t order_bytes(int64_t n) {
 
 int64_t order_slots(int64_t n) { return order_used(n) ? kXcds * order_chunk(n) : n; }
 
-// Which ordered runs may take the persistent walk (run_seg still takes the
-// one-launch kernel for a walk of at most one round of resident waves).  The
-// fp64 walker holds five waves per SIMD either way, and the persistent walk is
-// faster at every size measured beyond one round.  The mixed walker keeps six
-// waves in the persistent loop only with
-// a small spill: that pays while the tail is a large share of the launch (5%
-// faster at 1e6 walkers, 2.5 rounds of resident waves) but not for long
-// launches (3% slower at 1e7 walkers), so the mixed form takes it up to eight
-// rounds of its 6 x 1024 resident waves.
-constexpr int64_t kMixedSegMaxWalkers = int64_t(8) * 6 * 1024 * 64;
-
+// Ordered runs that may take the persistent walk get its state buffer: up to
+// 4.5 rounds of the largest resident wave count of the walkers (six per
+// SIMD); run_seg makes the exact choice from the kernel's occupancy.
 size_t seg_state_bytes(int precision, int n_shapes, int64_t n) {
-    if (!order_used(n) || (precision != RMS_FP64 && n > kMixedSegMaxWalkers)) return 0;
+    if (!order_used(n)) return 0;
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return 0;
+    const int64_t max_walkers = int64_t(9) * cus * 4 * 6 * kWave / 2;
+    if (n > max_walkers) return 0;
     return static_cast<size_t>(order_slots(n)) * walker_state_bytes(precision, 2, n_shapes);
 }
 
