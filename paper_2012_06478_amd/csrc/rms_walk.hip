@@ -242,7 +242,7 @@ __global__ __launch_bounds__(kBlock) void order_scatter_kernel(const uint32_t* k
 // every step ends with a partly filled last round of resident waves and a
 // ramp-down while they finish; at 1e6 walkers that is 5-8% of the launch.
 // Here the grid holds only as many blocks as can be resident, and each wave
-// takes work items (64 slots, segment of about n_steps/16 steps, 1024 to 4096) from the
+// takes work items (64 slots, segment of about n_steps/16 steps, 2048 to 4096) from the
 // queue of its XCD (block b serves queue b mod 8, the XCD the walker order
 // gave those slots) in segment-major order, so all walkers advance together
 // and the last partial round is one short segment.  A walker state lives in
@@ -258,7 +258,11 @@ __global__ __launch_bounds__(kBlock) void order_scatter_kernel(const uint32_t* k
 // fetches broadcasts the item with readfirstlane.
 
 constexpr uint32_t kSegPollLimit = 1u << 20;  // polls of 1-2 us: about a second
-constexpr int64_t kSegMinSteps = 1024;
+// At least 2048 steps a segment: fewer segment boundaries (each moves the
+// walker states through HBM) against a shorter last segment; at 1e6 walkers x
+// 1e4 steps five segments beat ten by 1.6% (FP64 63.0 against 64.1 ms, mixed
+// 52.7 against 53.4 ms) and two lose 3%.
+constexpr int64_t kSegMinSteps = 2048;
 // At most 4096 steps a segment (about 10 ms at full occupancy), so that a
 // wave never waits anywhere near the poll limit, however long the walk.
 constexpr int64_t kSegMaxSteps = 4096;

@@ -214,14 +214,15 @@ def test_records_errors():
 
 @pytest.mark.parametrize("precision", [rms.RMS_FP64, rms.RMS_MIXED])
 def test_long_walk_persistent_equals_packed(precision):
-    """400000 walkers (more than one round of resident waves: the persistent
-    walk) x 70000 steps (segments capped at 4096 steps: 18 segments): rms_run
-    equals the packed intervals of rms_run_record bit for bit."""
+    """700000 walkers (2.1 rounds of resident waves FP64, 1.8 mixed: the
+    persistent walk) x 70000 steps (segments capped at 4096 steps: 18
+    segments): rms_run equals the packed intervals of rms_run_record bit for
+    bit."""
     lab = cylinder_z(24, 7.0)
     D, kap = [2.0, 1.7], np.array([[0.0, 0.02], [0.02, 0.0]])
-    kw = dict(seed=12, n_walkers=400_000, n_steps=70_000, dt=2e-4, dirs=six_dirs(),
+    kw = dict(seed=12, n_walkers=700_000, n_steps=70_000, dt=2e-4, dirs=six_dirs(),
               bvals=[0.0, 1.0], waveform=pgse(70_000, 2e-4, 2.0, 10.0), precision=precision)
-    print(f"[case] long walk 4e5 x 7e4 precision={precision}", flush=True)
+    print(f"[case] long walk 7e5 x 7e4 precision={precision}", flush=True)
     sub = rms.rms_create_substrate(lab, 0.1, D, kap)
     e = rms.rms_run(sub, **kw)
     g = rms.rms_run_record(sub, record_steps=[35_001, 70_000], **kw)
