@@ -1,0 +1,45 @@
+"""CPU checks of bench.py's contract: one GPU only, the walk kernel it names
+for a workload, and the traffic figure tied to the profiled kernel sources."""
+import os
+import subprocess
+import sys
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import bench  # noqa: E402
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+
+
+def _case(n_walkers, n_shapes=1, dtype=np.uint16):
+    return dict(labels=np.zeros((4, 4, 4), dtype), n_walkers=n_walkers, n_steps=10,
+                waveform=np.zeros((n_shapes, 10)))
+
+
+def test_walk_kernel_name_follows_the_launch_rule():
+    # persistent between 1.5 and 4.5 rounds of resident waves (5 x 1024 waves
+    # of 64 lanes FP64, 6 x 1024 mixed), one launch elsewhere
+    assert "walk_seg_kernel" in bench.walk_kernel_name(True, _case(1_000_000))
+    assert "walk_kernel<" in bench.walk_kernel_name(True, _case(400_000))
+    assert "walk_kernel<" in bench.walk_kernel_name(True, _case(3_000_000))
+    assert "walk_seg_kernel" in bench.walk_kernel_name(False, _case(700_000))
+    assert "walk_kernel<" in bench.walk_kernel_name(False, _case(10_000_000, 2))
+    assert "<uint16,2,false>" in bench.walk_kernel_name(False, _case(10_000_000, 2))
+    assert "<uint8,1,false>" in bench.walk_kernel_name(True, _case(10_000, 1, np.uint8))
+
+
+def test_traffic_needs_the_profiled_sources():
+    """The traffic figure is reported only while the walk sources hash to the
+    value recorded with the counters."""
+    sha = bench.kernel_sha()
+    assert len(sha) == 16 and int(sha, 16) >= 0
+    t = bench.traffic_from_profile("ellipsoids200_u16", "fp64")
+    assert t is None or t > 0
