@@ -219,7 +219,8 @@ int prepare_run(const rms_substrate* sub, const rms_params* params, uint64_t see
     r.n_sig = static_cast<int>(n_sig64);
     r.width = RMS_DUMP_WIDTH(n_shapes);
     r.n_acc = kAccFixed + 2 * r.n_sig;
-    r.n_blocks = static_cast<int>((n_walkers + kBlock - 1) / kBlock);
+    // blocks of the contribution kernel: each thread folds up to four walkers
+    r.n_blocks = static_cast<int>((n_walkers + 4 * kBlock - 1) / (4 * kBlock));
     r.n_res = r.n_acc + 2 * n_dirs;
 
     const double* D = sub->D.data();

@@ -4,7 +4,7 @@
 //
 // Three kernels, all in double precision and in a fixed order, so a result
 // depends only on the walker count and never on scheduling:
-//   contrib   one lane per walker computes its accumulated values (alpha,
+//   contrib   each lane computes the accumulated values of up to four walkers (alpha,
 //             alpha dx_i dx_j, alpha dx_i dx_j dx_k dx_l, the event counters and
 //             alpha (cos phi, -sin phi) for every signal); each wave sums them
 //             with cross-lane shuffles, the block adds its four waves in order
@@ -25,25 +25,52 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
+// Each thread folds up to kFold walkers (block b covers walkers b W .. b W +
+// W - 1, W = fold x kBlock, fold = ceil(n_walkers / (n_blocks kBlock)) <=
+// kFold; walker j kBlock + t of the block goes to thread t), adding their
+// values in a fixed order before the wave sums, so the cross-lane work is
+// shared by several walkers.
+constexpr int kFold = 4;
+
 __global__ __launch_bounds__(kBlock) void contrib_kernel(ReducePlan p) {
     extern __shared__ double lds[];  // [n_acc][kWaves]
-    const int64_t w = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
-    const bool valid = w < p.n_walkers;
-    const double* st = p.wstate + (valid ? w : 0) * p.width;
+    const int64_t span = static_cast<int64_t>(p.n_blocks) * kBlock;
+    const int fold = static_cast<int>((p.n_walkers + span - 1) / span);  // <= kFold (host)
+    const int64_t w0 = static_cast<int64_t>(blockIdx.x) * fold * kBlock + threadIdx.x;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const double alpha = valid ? exp(-st[3]) : 0.0;
-    const double X[3] = {valid ? st[0] : 0.0, valid ? st[1] : 0.0, valid ? st[2] : 0.0};
+    bool valid[kFold];
+    const double* st[kFold];
+    double alpha[kFold], X[kFold][3];
+#pragma unroll
+    for (int j = 0; j < kFold; ++j) {
+        const int64_t w = w0 + static_cast<int64_t>(j) * kBlock;
+        valid[j] = j < fold && w < p.n_walkers;
+        st[j] = p.wstate + (valid[j] ? w : 0) * p.width;
+        alpha[j] = valid[j] ? exp(-st[j][3]) : 0.0;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) X[j][a] = valid[j] ? st[j][a] : 0.0;
+    }
 
     auto put = [&](int k, double v) {
         v = wave_sum(v);
         if (lane == 0) lds[k * kWaves + wave] = v;
     };
-    put(0, alpha);
+    {
+        double v = 0.0;
+#pragma unroll
+        for (int j = 0; j < kFold; ++j) v += alpha[j];
+        put(0, v);
+    }
     int k = 1;
 #pragma unroll
     for (int a = 0; a < 3; ++a)
 #pragma unroll
-        for (int b = a; b < 3; ++b) put(k++, alpha * X[a] * X[b]);
+        for (int b = a; b < 3; ++b) {
+            double v = 0.0;
+#pragma unroll
+            for (int j = 0; j < kFold; ++j) v += alpha[j] * X[j][a] * X[j][b];
+            put(k++, v);
+        }
 #pragma unroll
     for (int a = 0; a < 3; ++a)
 #pragma unroll
@@ -51,22 +78,41 @@ __global__ __launch_bounds__(kBlock) void contrib_kernel(ReducePlan p) {
 #pragma unroll
             for (int c = b; c < 3; ++c)
 #pragma unroll
-                for (int d = c; d < 3; ++d) put(k++, alpha * X[a] * X[b] * X[c] * X[d]);
-    put(22, valid ? st[12] : 0.0);
-    put(23, valid ? st[13] : 0.0);
-    put(24, valid ? st[14] : 0.0);
+                for (int d = c; d < 3; ++d) {
+                    double v = 0.0;
+#pragma unroll
+                    for (int j = 0; j < kFold; ++j)
+                        v += alpha[j] * X[j][a] * X[j][b] * X[j][c] * X[j][d];
+                    put(k++, v);
+                }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        double v = 0.0;
+#pragma unroll
+        for (int j = 0; j < kFold; ++j) v += valid[j] ? st[j][12 + c] : 0.0;
+        put(22 + c, v);
+    }
 
     const int per_shape = p.n_shapes > 0 ? p.n_sig / p.n_shapes : 0;
     for (int s = 0; s < p.n_shapes; ++s) {
-        const double f0 = valid ? st[kDumpFixed + 3 * s] : 0.0;
-        const double f1 = valid ? st[kDumpFixed + 3 * s + 1] : 0.0;
-        const double f2 = valid ? st[kDumpFixed + 3 * s + 2] : 0.0;
+        double f[kFold][3];
+#pragma unroll
+        for (int j = 0; j < kFold; ++j)
+#pragma unroll
+            for (int a = 0; a < 3; ++a) f[j][a] = valid[j] ? st[j][kDumpFixed + 3 * s + a] : 0.0;
         for (int q = s * per_shape; q < (s + 1) * per_shape; ++q) {
-            const double phi = fma(p.kg[3 * q], f0, fma(p.kg[3 * q + 1], f1, p.kg[3 * q + 2] * f2));
-            double sn, cs;
-            sincos(phi, &sn, &cs);
-            put(kAccFixed + 2 * q, alpha * cs);
-            put(kAccFixed + 2 * q + 1, -alpha * sn);
+            double re = 0.0, im = 0.0;
+#pragma unroll
+            for (int j = 0; j < kFold; ++j) {
+                const double phi =
+                    fma(p.kg[3 * q], f[j][0], fma(p.kg[3 * q + 1], f[j][1], p.kg[3 * q + 2] * f[j][2]));
+                double sn, cs;
+                sincos(phi, &sn, &cs);
+                re += alpha[j] * cs;
+                im -= alpha[j] * sn;
+            }
+            put(kAccFixed + 2 * q, re);
+            put(kAccFixed + 2 * q + 1, im);
         }
     }
     __syncthreads();
