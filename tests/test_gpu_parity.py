@@ -165,6 +165,21 @@ def test_degenerate_sizes(n_walkers, n_steps):
         assert np.all(g["dump"][:, 0:3] == 0.0)
 
 
+@pytest.mark.parametrize("n_walkers", [1023, 1024, 1025, 3073, 4097])
+def test_reduction_fold_boundaries(n_walkers):
+    """Walker counts around the reduction's fold of up to four walkers per
+    thread (1024 walkers a block): every walker is counted once, so the
+    summary equals the oracle's to the plain FP64 bars."""
+    lab = cylinder_z(16, 5.0)
+    kap = np.array([[0.0, 0.1], [0.1, 0.0]])
+    n, dt = 60, 2e-4
+    g, o = _both(lab, 0.1, np.array([2.0, 1.6]), kap, np.array([70.0, 50.0]), seed=31,
+                 n_walkers=n_walkers, n_steps=n, dt=dt, waveform=pgse(n, dt, 0.002, 0.006),
+                 dirs=six_dirs(), bvals=[0.0, 1.0, 4.0])
+    _assert_walkers(g, o, 1e-9)
+    _assert_summary(g, o, 1e-9)
+
+
 def test_four_shapes_and_anisotropic_volume():
     lab = uniform_volume(5, 7, 3)
     lab[1, 2:5, 1:4] = 1
