@@ -206,7 +206,10 @@ void rms_destroy_substrate(rms_substrate* sub);
  *   precision    RMS_FP64 or RMS_MIXED;
  *   hip_stream   hipStream_t to run on (NULL = the null stream);
  *   out          results (see rms_result).
- * Blocks until the results are in host memory. */
+ * Blocks until the results are in host memory.  A run's device memory comes
+ * from the device's default stream-ordered pool (hipMallocAsync); the first
+ * run on a device sets that pool to keep up to 4 GiB of freed memory for the
+ * next run instead of returning it to the driver at each synchronization. */
 int rms_run(const rms_substrate* sub, const rms_params* params, uint64_t seed, int64_t n_walkers,
             int64_t n_steps, double dt_ms, int n_shapes, const double* waveform, int n_dirs,
             const double* dirs, int n_b, const double* bvals, int precision, void* hip_stream,

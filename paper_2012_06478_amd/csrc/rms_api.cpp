@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <mutex>
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -339,9 +340,28 @@ size_t device_bytes(const RunSetup& r, bool resumable) {
     return b + 64 * 1024;  // allocation granularity slack
 }
 
+// Freed run memory stays in the device's default stream-ordered pool, up to
+// kPoolKeepBytes, instead of going back to the driver at each synchronization,
+// so back-to-back runs do not map their memory again.
+constexpr uint64_t kPoolKeepBytes = uint64_t(4) << 30;
+
+void keep_pool_memory() {
+    static std::once_flag once[64];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return;
+    std::call_once(once[dev], [dev] {
+        hipMemPool_t pool = nullptr;
+        if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess && pool) {
+            uint64_t keep = kPoolKeepBytes;
+            hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
+        }
+    });
+}
+
 int DeviceRun::create(const rms_substrate& sub, const RunSetup& r, bool resumable,
                       hipStream_t stream) {
     s = stream;
+    keep_pool_memory();
     const size_t L = static_cast<size_t>(sub.n_labels);
     // One device allocation for the whole run, carved into 256-byte aligned
     // pieces (an allocation and a free per buffer cost about 90 us each).
