@@ -1,6 +1,6 @@
 """Parity of the HIP walker (through the C ABI) with the CPU oracle.
 
-Bars (stated by the method's specification of this build):
+Bars (the acceptance bars of this implementation):
   - per walker: final displacement within 1e-5 um, every integer field (end
     label and voxel, start label, event counts) identical;
   - signals within 1e-3 absolute.
