@@ -229,3 +229,28 @@ def test_long_walk_persistent_equals_packed(precision):
     sub.close()
     _same_end(g, e)
     assert g["n_permeations"] > 0
+
+
+def test_records_on_a_torch_stream():
+    """rms_run_record on a torch stream of the caller (its own second stream
+    joins it) equals the run on the null stream bit for bit, and leaves the
+    caller's stream usable."""
+    import torch
+    lab, D, kap, T2 = _cells()
+    kw = dict(seed=19, n_walkers=5000, n_steps=500, dt=2e-4, dirs=six_dirs(), bvals=[0.0, 1.0],
+              waveform=pgse(500, 2e-4, 0.03, 0.06))
+    print("[case] records on a torch stream", flush=True)
+    sub = rms.rms_create_substrate(lab, 0.1, D, kap, T2)
+    try:
+        a = rms.rms_run_record(sub, record_steps=[50, 250, 499], **kw)
+        s = torch.cuda.Stream()
+        b = rms.rms_run_record(sub, record_steps=[50, 250, 499], stream=s, **kw)
+        with torch.cuda.stream(s):
+            x = torch.ones(1000, device="cuda", dtype=torch.float64).sum()
+        s.synchronize()
+        assert float(x) == 1000.0
+    finally:
+        sub.close()
+    _same_end(a, b)
+    for k in ("sum_alpha", "m2", "m4", "D", "K"):
+        assert np.array_equal(a["records"][k], b["records"][k]), k
