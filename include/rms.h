@@ -26,7 +26,7 @@
 extern "C" {
 #endif
 
-#define RMS_ABI_VERSION 2
+#define RMS_ABI_VERSION 3
 
 /* Error codes. */
 #define RMS_OK 0
@@ -36,11 +36,14 @@ extern "C" {
 #define RMS_E_PROB_TOO_LARGE (-4)      /* a permeation probability > RMS_MAX_PERM_PROB */
 #define RMS_E_UNBALANCED_WAVEFORM (-5) /* |sum_i G_i| > 1e-9 sum_i |G_i| for a shape */
 #define RMS_E_OOM (-6)                 /* device or host allocation failed */
-#define RMS_E_DEVICE (-7)              /* a HIP runtime call failed, or a wave of the
-                                          persistent walk gave up a bounded wait for
-                                          an earlier segment (no result) */
+#define RMS_E_DEVICE (-7)              /* a HIP runtime call failed (no result) */
 #define RMS_E_BUSY (-8)                /* server: request cannot be admitted now */
 #define RMS_E_TIMEOUT (-9)             /* server: wait timed out */
+#define RMS_E_WAIT_GAVE_UP (-10)       /* a wave of the persistent walk gave up its
+                                          bounded wait for the previous segment of
+                                          its walkers; every wave then stopped and
+                                          the run has no result (the substrate and
+                                          later runs are unaffected) */
 
 /* Permeation rules (rms_params.perm_model). */
 #define RMS_PERM_KAPPA 0  /* Eq. (perm-prob-general); with concentrations Eq. (gen-perm-prob) */
@@ -49,6 +52,14 @@ extern "C" {
 /* Precision forms of rms_run. */
 #define RMS_FP64 0  /* double-precision walk and reductions */
 #define RMS_MIXED 1 /* int32 voxel + fp32 offset walk, fp64 reductions */
+
+/* Walk kernels (rms_result.walk_kernel, RMS_OPT_WALK_KERNEL). */
+#define RMS_WALK_AUTO (-1)       /* option value: the library chooses (default) */
+#define RMS_WALK_ONE_LAUNCH 0    /* one thread per walker, every step in one launch */
+#define RMS_WALK_PERSISTENT 1    /* resident waves take (64 walkers, segment of steps)
+                                    items from per-XCD queues */
+#define RMS_WALK_PACKED 2        /* launches over step ranges with the walker states in
+                                    device memory (rms_run_record, the server) */
 
 /* Size limits. */
 #define RMS_MAX_SHAPES 4     /* gradient waveform shapes per run */
@@ -160,6 +171,9 @@ typedef struct {
                                    stream; server: 0 (launches are shared) */
     double queue_s;             /* server: submit to admission; rms_run: 0 */
     double* walker_dump;
+    int walk_kernel;            /* RMS_WALK_ONE_LAUNCH or RMS_WALK_PERSISTENT (rms_run),
+                                   RMS_WALK_PACKED (rms_run_record, the server): the walk
+                                   kernel that ran */
 } rms_result;
 
 /* ABI version (RMS_ABI_VERSION of the built library). */
@@ -167,6 +181,27 @@ int rms_abi_version(void);
 
 /* Description of the last failure on the calling thread ("" if none). */
 const char* rms_last_error(void);
+
+/* Process-wide options of the walk launch, for measurements and tests of the
+ * launch paths (every run afterwards uses them; not thread-safe against runs
+ * in flight).  Neither option changes a result: a walker's trajectory depends
+ * only on (seed, walker, step).
+ *   RMS_OPT_WALK_KERNEL     RMS_WALK_AUTO (default: the persistent walk when
+ *                           the walkers fill between 1.5 and 4.5 rounds of
+ *                           resident waves, else one launch),
+ *                           RMS_WALK_ONE_LAUNCH or RMS_WALK_PERSISTENT (taken
+ *                           by runs of at most 4.5 rounds of six resident waves
+ *                           per SIMD, which hold its state buffer; others run
+ *                           one launch);
+ *   RMS_OPT_SEG_POLL_LIMIT  polls (each a sleep of about a microsecond) a wave
+ *                           of the persistent walk makes for the previous
+ *                           segment of its walkers before it gives up and the
+ *                           run fails with RMS_E_WAIT_GAVE_UP; >= 0, default
+ *                           2^20 (about a second).
+ * RMS_E_INVALID_ARG for an unknown option or value. */
+#define RMS_OPT_WALK_KERNEL 1
+#define RMS_OPT_SEG_POLL_LIMIT 2
+int rms_set_option(int option, int64_t value);
 
 /* Build a device-resident substrate (sections 2.1.1 and 2.2 item 1).
  *   labels      host array of nx*ny*nz labels, x fastest then y then z,
@@ -207,9 +242,10 @@ void rms_destroy_substrate(rms_substrate* sub);
  *   hip_stream   hipStream_t to run on (NULL = the null stream);
  *   out          results (see rms_result).
  * Blocks until the results are in host memory.  A run's device memory comes
- * from the device's default stream-ordered pool (hipMallocAsync); the first
- * run on a device sets that pool to keep up to 4 GiB of freed memory for the
- * next run instead of returning it to the driver at each synchronization. */
+ * from a stream-ordered pool the library creates on each device at its first
+ * run there and keeps until the process ends; the pool holds up to 4 GiB of
+ * freed memory for the next run instead of returning it to the driver at
+ * each synchronization (the device's default pool is not touched). */
 int rms_run(const rms_substrate* sub, const rms_params* params, uint64_t seed, int64_t n_walkers,
             int64_t n_steps, double dt_ms, int n_shapes, const double* waveform, int n_dirs,
             const double* dirs, int n_b, const double* bvals, int precision, void* hip_stream,

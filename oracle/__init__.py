@@ -87,6 +87,9 @@ def _load():
     lib.rmso_mt_prob.restype = C.c_double
     lib.rmso_conc_perm_probs.argtypes = [C.c_double] * 6 + [C.c_int, C.c_double, d_p, d_p]
     lib.rmso_conc_perm_probs.restype = None
+    lib.rmso_conc_tables.argtypes = [C.c_int, d_p, d_p, u8_p, d_p, C.c_double, C.c_int,
+                                     C.c_double, u64_p]
+    lib.rmso_conc_tables.restype = C.c_int
     _lib = lib
     return lib
 
@@ -152,6 +155,23 @@ def tables(D, kappa, T2, dead, dt, voxel_um):
     if rc:
         raise OracleError(rc)
     return sigma, thr.reshape(n, n), inv
+
+
+def conc_tables(D, kappa, dead, conc, lam, model, dt):
+    """Permeation thresholds [n, n] (uint64, floor(P 2^32)) with spin
+    concentrations (App. C, general case; model 1: Baxter's rule)."""
+    D = np.ascontiguousarray(D, np.float64)
+    n = D.size
+    kap = None if kappa is None else np.ascontiguousarray(kappa, np.float64).reshape(n * n)
+    dd = None if dead is None else np.ascontiguousarray(dead, np.uint8)
+    cc = None if conc is None else np.ascontiguousarray(conc, np.float64)
+    thr = np.zeros(n * n, np.uint64)
+    rc = _load().rmso_conc_tables(n, _ptr(D, C.c_double), _ptr(kap, C.c_double),
+                                  _ptr(dd, C.c_uint8), _ptr(cc, C.c_double), float(lam),
+                                  int(model), dt, _ptr(thr, C.c_uint64))
+    if rc:
+        raise OracleError(rc)
+    return thr.reshape(n, n)
 
 
 def bscale(waveform, dt, bvals):

@@ -187,9 +187,9 @@ static uint64_t threshold_of(double P) {
 }
 
 /* Permeation thresholds with spin concentrations (rmso_conc_perm_probs for
- * each pair a < b of labels that are not dead, side 1 = a).  A permeation
- * word is 32 bits, so a probability of 1 (Baxter's rule from the low-flux
- * side) is applied as 1 - 2^-32, the largest threshold a word can be below. */
+ * each pair a < b of labels that are not dead, side 1 = a).  A probability of
+ * 1 (Baxter's rule from the low-flux side) is the threshold 2^32, which every
+ * 32-bit permeation word lies below. */
 int rmso_conc_tables(int n_labels, const double* D, const double* kappa, const uint8_t* dead,
                      const double* conc, double lambda, int model, double dt, uint64_t* thresh) {
     if (model != 0 && model != 1) return RMSO_E_INVALID_ARG;
@@ -204,10 +204,8 @@ int rmso_conc_tables(int n_labels, const double* D, const double* kappa, const u
             double P12, P21;
             rmso_conc_perm_probs(k, D[a], D[b], conc ? conc[a] : 1.0, conc ? conc[b] : 1.0,
                                  lambda, model, dt, &P12, &P21);
-            const uint64_t tmax = 4294967295u;
-            const uint64_t t12 = threshold_of(P12), t21 = threshold_of(P21);
-            thresh[a * n_labels + b] = t12 < tmax ? t12 : tmax;
-            thresh[b * n_labels + a] = t21 < tmax ? t21 : tmax;
+            thresh[a * n_labels + b] = threshold_of(P12);
+            thresh[b * n_labels + a] = threshold_of(P21);
         }
     return RMSO_OK;
 }

@@ -29,11 +29,20 @@ RMS_MAX_SIGNALS = 960
 RMS_MAX_LABELS = 4096
 RMS_MAX_PERM_PROB = 0.1
 RMS_DUMP_FIXED = 15
+RMS_WALK_AUTO = -1
+RMS_WALK_ONE_LAUNCH = 0
+RMS_WALK_PERSISTENT = 1
+RMS_WALK_PACKED = 2
+RMS_OPT_WALK_KERNEL = 1
+RMS_OPT_SEG_POLL_LIMIT = 2
+RMS_E_WAIT_GAVE_UP = -10
 ERROR_NAMES = {
     -1: "RMS_E_INVALID_ARG", -2: "RMS_E_LABEL_RANGE", -3: "RMS_E_STEP_TOO_LARGE",
     -4: "RMS_E_PROB_TOO_LARGE", -5: "RMS_E_UNBALANCED_WAVEFORM", -6: "RMS_E_OOM",
-    -7: "RMS_E_DEVICE", -8: "RMS_E_BUSY", -9: "RMS_E_TIMEOUT",
+    -7: "RMS_E_DEVICE", -8: "RMS_E_BUSY", -9: "RMS_E_TIMEOUT", -10: "RMS_E_WAIT_GAVE_UP",
 }
+WALK_KERNELS = {RMS_WALK_ONE_LAUNCH: "one launch", RMS_WALK_PERSISTENT: "persistent",
+                RMS_WALK_PACKED: "packed"}
 DUMP_FIELDS = ["dx", "dy", "dz", "R", "label", "ix", "iy", "iz", "ox", "oy", "oz",
                "label0", "n_face", "n_hit", "n_perm"]
 
@@ -66,7 +75,7 @@ class _Result(C.Structure):
                 ("n_membrane_hits", C.c_int64), ("n_permeations", C.c_int64),
                 ("max_perm_prob", C.c_double), ("max_step_over_voxel", C.c_double),
                 ("wall_s", C.c_double), ("kernel_ms", C.c_double), ("queue_s", C.c_double),
-                ("walker_dump", C.POINTER(C.c_double))]
+                ("walker_dump", C.POINTER(C.c_double)), ("walk_kernel", C.c_int)]
 
 
 class _Request(C.Structure):
@@ -102,6 +111,8 @@ def _load():
     dp, i64p, u8p = C.POINTER(C.c_double), C.POINTER(C.c_int64), C.POINTER(C.c_uint8)
     lib.rms_abi_version.restype = C.c_int
     lib.rms_last_error.restype = C.c_char_p
+    lib.rms_set_option.argtypes = [C.c_int, C.c_int64]
+    lib.rms_set_option.restype = C.c_int
     lib.rms_create_substrate.argtypes = [C.c_void_p, C.c_int, i64p, C.c_double, C.c_int, dp, dp,
                                          dp, u8p, C.POINTER(C.c_void_p)]
     lib.rms_create_substrate.restype = C.c_int
@@ -138,7 +149,7 @@ def _load():
 def exported_symbols() -> list[str]:
     """Names the library exports through the C ABI (for load checks)."""
     lib = _load()
-    names = ["rms_abi_version", "rms_last_error", "rms_create_substrate",
+    names = ["rms_abi_version", "rms_last_error", "rms_set_option", "rms_create_substrate",
              "rms_destroy_substrate", "rms_run", "rms_run_record", "rms_spherical_mean",
              "rms_cumulant_fit", "rms_server_create", "rms_server_submit",
              "rms_server_poll", "rms_server_wait", "rms_server_stats_get", "rms_server_destroy"]
@@ -151,6 +162,11 @@ def rms_abi_version() -> int:
 
 def rms_last_error() -> str:
     return _load().rms_last_error().decode()
+
+
+def rms_set_option(option: int, value: int) -> None:
+    """Process-wide launch option (``RMS_OPT_WALK_KERNEL``, ``RMS_OPT_SEG_POLL_LIMIT``)."""
+    _check(_load().rms_set_option(int(option), int(value)))
 
 
 def _check(rc: int):
@@ -191,11 +207,13 @@ def rms_create_substrate(labels, voxel_um, D, kappa=None, T2=None, dead=None) ->
     if lab.ndim != 3 or lab.dtype not in (np.uint8, np.uint16):
         raise TypeError("labels must be a 3d uint8 or uint16 array")
     dims = np.array(lab.shape[::-1], np.int64)
-    Dv = np.ascontiguousarray(D, np.float64)
+    Dv = np.ascontiguousarray(D, np.float64).reshape(-1)
     n = Dv.size
-    kap = None if kappa is None else np.ascontiguousarray(kappa, np.float64).reshape(n * n)
-    t2 = None if T2 is None else np.ascontiguousarray(T2, np.float64)
-    dd = None if dead is None else np.ascontiguousarray(dead, np.uint8)
+    kap = _sized(kappa, n * n, "kappa")
+    t2 = _sized(T2, n, "T2")
+    dd = None if dead is None else np.ascontiguousarray(dead, np.uint8).reshape(-1)
+    if dd is not None and dd.size != n:
+        raise ValueError(f"dead must have {n} entries (one per label), not {dd.size}")
     h = C.c_void_p()
     rc = lib.rms_create_substrate(lab.ctypes.data, lab.dtype.itemsize,
                                   dims.ctypes.data_as(C.POINTER(C.c_int64)), float(voxel_um), n,
@@ -218,27 +236,44 @@ def _stream_handle(stream):
     return int(stream.cuda_stream)  # torch.cuda.Stream (HIP stream on ROCm)
 
 
+def _sized(a, n, name):
+    """a as a flat contiguous float64 array of exactly n entries (or None):
+    the library reads n entries through the pointer."""
+    if a is None:
+        return None
+    v = np.ascontiguousarray(a, np.float64).reshape(-1)
+    if v.size != n:
+        raise ValueError(f"{name} must have {n} entries, not {v.size}")
+    return v
+
+
 def _protocol(n_steps, waveform, dirs, bvals):
     W = (np.zeros((0, n_steps)) if waveform is None
          else np.ascontiguousarray(np.atleast_2d(waveform), np.float64))
-    g = (np.zeros((0, 3)) if dirs is None
-         else np.ascontiguousarray(dirs, np.float64).reshape(-1, 3))
-    b = np.zeros(0) if bvals is None else np.ascontiguousarray(bvals, np.float64)
+    if W.ndim != 2 or (W.shape[0] > 0 and W.shape[1] != int(n_steps)):
+        raise ValueError(f"waveform must be [n_shapes, n_steps] with n_steps = {int(n_steps)}, "
+                         f"not {list(W.shape)}")
+    d = None if dirs is None else np.ascontiguousarray(dirs, np.float64)
+    if d is not None and (d.size % 3 != 0 or (d.ndim == 2 and d.shape[1] != 3)):
+        raise ValueError(f"dirs must be [n_dirs, 3], not {list(d.shape)}")
+    g = np.zeros((0, 3)) if d is None else d.reshape(-1, 3)
+    b = np.zeros(0) if bvals is None else np.ascontiguousarray(bvals, np.float64).reshape(-1)
     return W, g, b
 
 
-def _params(params, keep):
+def _params(params, keep, n_labels=None):
+    """rms_params from a dict; with n_labels (the substrate's), every array is
+    checked to hold the entries the library reads."""
     if params is None:
         return None
-    Dv = np.ascontiguousarray(params["D"], np.float64)
-    kap = params.get("kappa")
-    kap = None if kap is None else np.ascontiguousarray(kap, np.float64).reshape(-1)
-    t2 = params.get("T2")
-    t2 = None if t2 is None else np.ascontiguousarray(t2, np.float64)
-    rho = params.get("rho")
-    rho = None if rho is None else np.ascontiguousarray(rho, np.float64).reshape(-1)
-    conc = params.get("conc")
-    conc = None if conc is None else np.ascontiguousarray(conc, np.float64)
+    Dv = np.ascontiguousarray(params["D"], np.float64).reshape(-1)
+    n = Dv.size
+    if n_labels is not None and n != n_labels:
+        raise ValueError(f"params D must have {n_labels} entries (one per label), not {n}")
+    kap = _sized(params.get("kappa"), n * n, "params kappa")
+    t2 = _sized(params.get("T2"), n, "params T2")
+    rho = _sized(params.get("rho"), n * n, "params rho")
+    conc = _sized(params.get("conc"), n, "params conc")
     keep += [Dv, kap, t2, rho, conc]
     return _Params(Dv.size, _dptr(Dv), _dptr(kap), _dptr(t2), _dptr(rho), _dptr(conc),
                    float(params.get("lam", 0.0)), int(params.get("perm_model", RMS_PERM_KAPPA)))
@@ -269,6 +304,7 @@ class _ResultBuffers:
             n_permeations=res.n_permeations, max_perm_prob=res.max_perm_prob,
             max_step_over_voxel=res.max_step_over_voxel, wall_s=res.wall_s,
             kernel_ms=res.kernel_ms, queue_s=res.queue_s,
+            walk_kernel=WALK_KERNELS.get(res.walk_kernel, str(res.walk_kernel)),
         )
 
 
@@ -284,7 +320,7 @@ def rms_run(sub: Substrate, *, seed, n_walkers, n_steps, dt, waveform=None, dirs
     lib = _load()
     W, g, b = _protocol(n_steps, waveform, dirs, bvals)
     keep = []
-    pp = _params(params, keep)
+    pp = _params(params, keep, sub.n_labels)
     rb = _ResultBuffers(W.shape[0], b.size, g.shape[0])
     wd = np.zeros((int(n_walkers), RMS_DUMP_FIXED + 3 * W.shape[0])) if dump else None
     rb.res.walker_dump = _dptr(wd) if wd is not None else None
@@ -310,7 +346,7 @@ def rms_run_record(sub: Substrate, *, seed, n_walkers, n_steps, dt, record_steps
     lib = _load()
     W, g, b = _protocol(n_steps, waveform, dirs, bvals)
     keep = []
-    pp = _params(params, keep)
+    pp = _params(params, keep, sub.n_labels)
     rb = _ResultBuffers(W.shape[0], b.size, g.shape[0])
     wd = np.zeros((int(n_walkers), RMS_DUMP_FIXED + 3 * W.shape[0])) if dump else None
     rb.res.walker_dump = _dptr(wd) if wd is not None else None
@@ -380,7 +416,7 @@ def rms_server_submit(srv, sub: Substrate, *, seed, n_walkers, n_steps, dt, wave
     lib = _load()
     W, g, b = _protocol(n_steps, waveform, dirs, bvals)
     keep = []
-    pp = _params(params, keep)
+    pp = _params(params, keep, sub.n_labels)
     q = _Request(sub.handle, None if pp is None else C.pointer(pp), int(seed) & (2**64 - 1),
                  int(n_walkers), int(n_steps), float(dt), W.shape[0], _dptr(W), g.shape[0],
                  _dptr(g), b.size, _dptr(b), int(precision))
@@ -411,7 +447,7 @@ def rms_server_destroy(srv) -> None:
     _load().rms_server_destroy(srv)
 
 
-__all__ = ["rms_abi_version", "rms_last_error", "rms_create_substrate", "rms_destroy_substrate",
+__all__ = ["rms_abi_version", "rms_last_error", "rms_set_option", "rms_create_substrate", "rms_destroy_substrate",
            "rms_run", "rms_run_record", "rms_spherical_mean", "rms_cumulant_fit",
            "rms_server_create", "rms_server_submit", "rms_server_poll",
            "rms_server_wait", "rms_server_stats_get", "rms_server_destroy", "Substrate", "RmsError", "RMS_FP64", "RMS_MIXED", "exported_symbols",

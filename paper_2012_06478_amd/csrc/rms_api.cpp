@@ -55,8 +55,9 @@ namespace {
 // kappa0 = kappa / (1 + kappa A), A = (ds_a/D_a r^lam + ds_b/D_b r^(lam-1)) C/2
 // (Eq. gen-kappa-correction); lam < 0 takes 1 / (1 + c_b sqrt(D_b) / (c_a
 // sqrt(D_a))).  Baxter's rule (Eq. alt-perm-prob1-2): from the side of larger
-// c sqrt(D) the probability is the ratio of the two, from the other 1; a
-// probability of 1 is applied as 1 - 2^-32 (the largest 32-bit threshold).
+// c sqrt(D) the probability is the ratio of the two, from the other 1.  The
+// thresholds are 64-bit, so a probability of 1 is the threshold 2^32 that
+// every 32-bit word lies below.
 struct PermModel {
     const double* conc;  // or null: all equal
     double lambda;
@@ -88,12 +89,13 @@ int build_tables(const rms_substrate& sub, const double* D, const double* kappa,
                     "step length " + std::to_string(t.max_sigma) +
                         " voxels: a step must be shorter than the voxel (at most three face "
                         "interactions per step)");
+    constexpr uint64_t kAlways = uint64_t(1) << 32;
     t.thr.assign(static_cast<size_t>(L) * L, 0u);
     for (int a = 0; a < L; ++a) {
         for (int b = 0; b < L; ++b) {
-            uint32_t th = 0;
+            uint64_t th = 0;
             if (a == b) {
-                th = 0xFFFFFFFFu;  // never consulted: equal labels pass
+                th = kAlways;  // never consulted: equal labels pass
             } else if (!sub.dead[a] && !sub.dead[b] && kappa) {
                 const double k = kappa[static_cast<size_t>(a) * L + b];
                 if (!(k >= 0.0) || !std::isfinite(k))
@@ -128,8 +130,8 @@ int build_tables(const rms_substrate& sub, const double* D, const double* kappa,
                         return fail(RMS_E_PROB_TOO_LARGE,
                                     "permeation probability " + std::to_string(P) +
                                         " > RMS_MAX_PERM_PROB (0.1): lower dt or kappa");
-                    th = P >= 1.0 ? 0xFFFFFFFFu
-                                  : static_cast<uint32_t>(std::floor(std::ldexp(P, 32)));
+                    th = P >= 1.0 ? kAlways
+                                  : static_cast<uint64_t>(std::floor(std::ldexp(P, 32)));
                 }
             }
             t.thr[static_cast<size_t>(a) * L + b] = th;
@@ -323,7 +325,7 @@ int prepare_run(const rms_substrate* sub, const rms_params* params, uint64_t see
 
 size_t device_bytes(const RunSetup& r, bool resumable) {
     const size_t L = static_cast<size_t>(r.sub->n_labels);
-    size_t b = L * (2 * sizeof(double) + 2 * sizeof(float)) + L * L * sizeof(uint32_t);
+    size_t b = L * (2 * sizeof(double) + 2 * sizeof(float)) + L * L * sizeof(uint64_t);
     b += r.thr_mt.size() * sizeof(uint32_t) + r.accept.size() * sizeof(uint64_t);
     if (!r.accept.empty()) b += static_cast<size_t>(r.n_walkers) * sizeof(uint32_t);
     b += r.gdt.size() * sizeof(double) + 2 * kTrigSize * sizeof(double);
@@ -340,28 +342,54 @@ size_t device_bytes(const RunSetup& r, bool resumable) {
     return b + 64 * 1024;  // allocation granularity slack
 }
 
-// Freed run memory stays in the device's default stream-ordered pool, up to
-// kPoolKeepBytes, instead of going back to the driver at each synchronization,
-// so back-to-back runs do not map their memory again.
+// Device memory of the runs comes from a stream-ordered pool of the
+// library's own, one per device (created at the first run there, kept until
+// the process ends), not from the device's default pool that other code in
+// the process may use.  Freed run memory stays in it, up to kPoolKeepBytes,
+// instead of going back to the driver at each synchronization, so
+// back-to-back runs do not map their memory again (0.2-0.4 ms a run).
 constexpr uint64_t kPoolKeepBytes = uint64_t(4) << 30;
+constexpr int kMaxDevices = 64;
 
-void keep_pool_memory() {
-    static std::once_flag once[64];
+hipError_t run_pool(hipMemPool_t* out) {
+    static std::mutex m;
+    static hipMemPool_t pools[kMaxDevices] = {};
     int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return;
-    std::call_once(once[dev], [dev] {
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(m);
+    if (!pools[dev]) {
+        hipMemPoolProps props{};
+        props.allocType = hipMemAllocationTypePinned;
+        props.handleTypes = hipMemHandleTypeNone;
+        props.location.type = hipMemLocationTypeDevice;
+        props.location.id = dev;
         hipMemPool_t pool = nullptr;
-        if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess && pool) {
-            uint64_t keep = kPoolKeepBytes;
-            hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
+        e = hipMemPoolCreate(&pool, &props);
+        if (e != hipSuccess) return e;
+        uint64_t keep = kPoolKeepBytes;
+        e = hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
+        if (e != hipSuccess) {
+            hipMemPoolDestroy(pool);
+            return e;
         }
-    });
+        pools[dev] = pool;
+    }
+    *out = pools[dev];
+    return hipSuccess;
+}
+
+hipError_t run_malloc(void** p, size_t bytes, hipStream_t s) {
+    hipMemPool_t pool = nullptr;
+    const hipError_t e = run_pool(&pool);
+    if (e != hipSuccess) return e;
+    return hipMallocFromPoolAsync(p, bytes, pool, s);
 }
 
 int DeviceRun::create(const rms_substrate& sub, const RunSetup& r, bool resumable,
                       hipStream_t stream) {
     s = stream;
-    keep_pool_memory();
     const size_t L = static_cast<size_t>(sub.n_labels);
     // One device allocation for the whole run, carved into 256-byte aligned
     // pieces (an allocation and a free per buffer cost about 90 us each).
@@ -375,7 +403,7 @@ int DeviceRun::create(const rms_substrate& sub, const RunSetup& r, bool resumabl
     const size_t o_it2 = take(L * sizeof(double));
     const size_t o_sigma_f = take(L * sizeof(float));
     const size_t o_it2_f = take(L * sizeof(float));
-    const size_t o_thr = take(L * L * sizeof(uint32_t));
+    const size_t o_thr = take(L * L * sizeof(uint64_t));
     const size_t o_thr_mt = take(r.thr_mt.size() * sizeof(uint32_t));
     const size_t o_accept = take(r.accept.size() * sizeof(uint64_t));
     const size_t o_start_try =
@@ -399,14 +427,14 @@ int DeviceRun::create(const rms_substrate& sub, const RunSetup& r, bool resumabl
     const size_t o_seg_state = take(seg_b);
     const size_t o_seg_ctl = take(seg_b > 0 ? seg_ctl_bytes(r.n_walkers) : 0);
     void* base = nullptr;
-    RMS_HIP(hipMallocAsync(&base, total, s));
+    RMS_HIP(run_malloc(&base, total, s));
     ptrs.push_back(base);
     uint8_t* const b = static_cast<uint8_t*>(base);
     double* d_sigma = reinterpret_cast<double*>(b + o_sigma);
     double* d_it2 = reinterpret_cast<double*>(b + o_it2);
     float* d_sigma_f = reinterpret_cast<float*>(b + o_sigma_f);
     float* d_it2_f = reinterpret_cast<float*>(b + o_it2_f);
-    uint32_t* d_thr = reinterpret_cast<uint32_t*>(b + o_thr);
+    uint64_t* d_thr = reinterpret_cast<uint64_t*>(b + o_thr);
     uint32_t* d_thr_mt = r.thr_mt.empty() ? nullptr : reinterpret_cast<uint32_t*>(b + o_thr_mt);
     uint64_t* d_accept = r.accept.empty() ? nullptr : reinterpret_cast<uint64_t*>(b + o_accept);
     uint32_t* d_start_try =
@@ -688,7 +716,8 @@ int rms_run(const rms_substrate* sub, const rms_params* params, uint64_t seed, i
     RMS_HIP(rms::launch_start_try(dr.wp, stream));
     RMS_HIP(rms::launch_order(dr.wp, stream));
     RMS_HIP(hipEventRecord(ev0, stream));
-    RMS_HIP(rms::launch_walk(dr.wp, precision, stream));
+    int kind = RMS_WALK_ONE_LAUNCH;
+    RMS_HIP(rms::launch_walk(dr.wp, precision, stream, &kind));
     RMS_HIP(hipEventRecord(ev1, stream));
     RMS_HIP(rms::launch_reduce(dr.rp, stream));
 
@@ -705,15 +734,37 @@ int rms_run(const rms_substrate* sub, const rms_params* params, uint64_t seed, i
                                hipMemcpyDeviceToHost, stream));
     RMS_HIP(hipStreamSynchronize(stream));
     if (seg_fail[0] != 0u)
-        return rms::fail(RMS_E_DEVICE, "walk: a wait for an earlier segment of a walker block "
-                                       "gave up; no result");
+        return rms::fail(RMS_E_WAIT_GAVE_UP,
+                         "walk: a wave of the persistent walk gave up waiting for the previous "
+                         "segment of its walkers; every wave stopped, no result");
     float ms = 0.0f;
     RMS_HIP(hipEventElapsedTime(&ms, ev0, ev1));
     rms::fill_result(r, res.data(), out);
     out->kernel_ms = ms;
     out->queue_s = 0.0;
+    out->walk_kernel = kind;
     out->wall_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     return RMS_OK;
+}
+
+int rms_set_option(int option, int64_t value) {
+    rms::clear_error();
+    switch (option) {
+        case RMS_OPT_WALK_KERNEL:
+            if (value != RMS_WALK_AUTO && value != RMS_WALK_ONE_LAUNCH &&
+                value != RMS_WALK_PERSISTENT)
+                return rms::fail(RMS_E_INVALID_ARG, "RMS_OPT_WALK_KERNEL: RMS_WALK_AUTO, "
+                                                    "RMS_WALK_ONE_LAUNCH or RMS_WALK_PERSISTENT");
+            rms::set_walk_choice(static_cast<int>(value));
+            return RMS_OK;
+        case RMS_OPT_SEG_POLL_LIMIT:
+            if (value < 0 || value > int64_t(0xFFFFFFFEu))
+                return rms::fail(RMS_E_INVALID_ARG, "RMS_OPT_SEG_POLL_LIMIT: 0 .. 2^32 - 2 polls");
+            rms::set_seg_poll_limit(static_cast<uint32_t>(value));
+            return RMS_OK;
+        default:
+            return rms::fail(RMS_E_INVALID_ARG, "unknown option " + std::to_string(option));
+    }
 }
 
 int rms_spherical_mean(int n_b, int n_dirs, const double* signal, double* out) {
@@ -829,7 +880,7 @@ int rms_run_record(const rms_substrate* sub, const rms_params* params, uint64_t 
                                      256 * 256;
     const size_t extra = o_wst + wst_b;
     void* xb = nullptr;
-    RMS_HIP(hipMallocAsync(&xb, extra, stream));
+    RMS_HIP(rms::run_malloc(&xb, extra, stream));
     dr.ptrs.push_back(xb);
     uint8_t* xbase = static_cast<uint8_t*>(xb);
     auto* d_plan = reinterpret_cast<rms::WalkPlan*>(xbase);
@@ -969,6 +1020,7 @@ int rms_run_record(const rms_substrate* sub, const rms_params* params, uint64_t 
                 rec->K_dir[static_cast<size_t>(k) * n_dirs + d] = v[rms::kAccFixed + n_dirs + d];
         }
     }
+    out->walk_kernel = RMS_WALK_PACKED;
     out->kernel_ms = ms;
     out->queue_s = 0.0;
     out->wall_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();

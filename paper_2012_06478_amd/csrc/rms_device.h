@@ -247,11 +247,12 @@ __device__ __forceinline__ uint32_t wrap_halo(const WalkPlan& p, uint32_t off, u
 }
 
 // Permeation threshold from label l into label nl (both below 4096, so the
-// byte offset 4 (l L + nl) fits 32 bits and l L is a 24-bit multiply).
-__device__ __forceinline__ uint32_t threshold(const WalkPlan& p, int l, int nl) {
+// byte offset 8 (l L + nl) fits 32 bits and l L is a 24-bit multiply): a
+// 64-bit floor(P 2^32), so that P = 1 (2^32) permeates on every word.
+__device__ __forceinline__ uint64_t threshold(const WalkPlan& p, int l, int nl) {
     const uint32_t off = (__umul24(static_cast<uint32_t>(l), static_cast<uint32_t>(p.n_labels)) +
-                          static_cast<uint32_t>(nl)) * 4u;
-    return *reinterpret_cast<const uint32_t*>(reinterpret_cast<const char*>(p.thr) + off);
+                          static_cast<uint32_t>(nl)) * 8u;
+    return *reinterpret_cast<const uint64_t*>(reinterpret_cast<const char*>(p.thr) + off);
 }
 
 // Saturation threshold for a walker in label l meeting label nl at an
@@ -438,7 +439,8 @@ struct WalkerF64T {
                 bool cross = true;
                 if (nl != l) {
                     ++nhit;
-                    [[maybe_unused]] uint32_t tp = 0u, tm = 0u;
+                    [[maybe_unused]] uint64_t tp = 0u;
+                    [[maybe_unused]] uint32_t tm = 0u;
                     if constexpr (MT) {  // both thresholds in one memory round trip
                         tp = threshold(p, l, nl);
                         tm = threshold_mt(p, l, nl);
@@ -656,7 +658,8 @@ struct WalkerMixedT {
                 bool cross = true;
                 if (nl != l) {
                     ++nhit;
-                    [[maybe_unused]] uint32_t tp = 0u, tm = 0u;
+                    [[maybe_unused]] uint64_t tp = 0u;
+                    [[maybe_unused]] uint32_t tm = 0u;
                     if constexpr (MT) {  // both thresholds in one memory round trip
                         tp = threshold(p, l, nl);
                         tm = threshold_mt(p, l, nl);

@@ -41,6 +41,10 @@ inline void fill_trig_table(double* cs) {
     }
 }
 
+// Stream-ordered device allocation from the library's own pool on the
+// current device (freed with hipFreeAsync).
+hipError_t run_malloc(void** p, size_t bytes, hipStream_t s);
+
 // Records a failure for rms_last_error() on the calling thread; returns code.
 int fail(int code, const std::string& msg);
 int hip_fail(const char* what, hipError_t e);
@@ -59,7 +63,7 @@ struct RunSetup {
     int n_acc = 0, width = 0, n_blocks = 0, n_res = 0;
     std::vector<double> sigma, inv_t2;
     std::vector<float> sigma_f, inv_t2_f;
-    std::vector<uint32_t> thr;
+    std::vector<uint64_t> thr;     // permeation thresholds floor(P 2^32) in [0, 2^32]
     std::vector<uint32_t> thr_mt;  // saturation thresholds (end of section 2.1.3), or empty
     std::vector<uint64_t> accept;  // start acceptance per label (spin concentrations), or empty
     double max_sigma = 0.0, max_p = 0.0;

@@ -39,7 +39,8 @@ struct WalkPlan {
     int n_labels;
     const double* sigma;    // [n_labels] step length per label, voxel units
     const double* inv_t2;   // [n_labels] 1/T2 (0 for none)
-    const uint32_t* thr;    // [n_labels^2] permeation thresholds: word < thr permeates
+    const uint64_t* thr;    // [n_labels^2] permeation thresholds floor(P 2^32) in [0, 2^32]:
+                            // a 32-bit word < thr permeates (2^32: always)
     const uint32_t* thr_mt; // [n_labels^2] saturation thresholds at absorbing membranes, or
                             // null: no membrane absorbs
     const float* sigma_f;   // fp32 copies for the mixed form
@@ -107,8 +108,15 @@ struct ReducePlan {
 
 constexpr int kAccFixed = 25;  // alpha, 6 M2, 15 M4, 3 counters
 
-// Whole walk of every walker of one run (precision RMS_FP64 or RMS_MIXED).
-hipError_t launch_walk(const WalkPlan& p, int precision, hipStream_t s);
+// Whole walk of every walker of one run (precision RMS_FP64 or RMS_MIXED);
+// *kind receives the walk kernel launched (RMS_WALK_ONE_LAUNCH or
+// RMS_WALK_PERSISTENT).
+hipError_t launch_walk(const WalkPlan& p, int precision, hipStream_t s, int* kind);
+// Options of the walk launch (rms_set_option): kernel choice (RMS_WALK_AUTO,
+// RMS_WALK_ONE_LAUNCH, RMS_WALK_PERSISTENT) and the persistent walk's poll
+// limit.
+void set_walk_choice(int choice);
+void set_seg_poll_limit(uint32_t polls);
 // A packed launch over several runs that share precision, label width, shape
 // count and whether membranes absorb (mt: every plan has thr_mt): each block advances its walkers by a range of steps, starting
 // from the stored state (or the start when step_begin == 0) and storing the

@@ -344,6 +344,7 @@ int rms_server_wait(rms_server* srv, rms_ticket ticket, double timeout_s, rms_re
     if (own->state == Request::kFailed) return rms::fail(own->rc, own->err);
     rms::fill_result(own->setup, own->res.data(), out);
     out->kernel_ms = 0.0;
+    out->walk_kernel = RMS_WALK_PACKED;
     out->wall_s = seconds_since(own->t_submit, own->t_done);
     out->queue_s = seconds_since(own->t_submit, own->t_admit);
     return RMS_OK;

@@ -12,6 +12,8 @@
 //                     join.  The arithmetic of a step is the same code as in
 //                     walk_kernel, so a walker's result does not depend on how
 //                     its steps were sliced.
+#include <atomic>
+
 #include "rms.h"
 #include "rms_device.h"
 
@@ -251,13 +253,18 @@ __global__ __launch_bounds__(kBlock) void order_scatter_kernel(const uint32_t* k
 // that item was handed out about one segment-round earlier, so the wait
 // almost never polls.  Only a running wave can hold an item, so every chain
 // of waits ends at a wave that is walking: no deadlock, whatever the number
-// of resident waves.  The wait is bounded all the same: past kSegPollLimit
+// of resident waves.  The wait is bounded all the same: past the poll limit
 // polls the wave raises the failure flag, every wave then stops taking items,
 // and the host reports the run as failed.  The loop has no block barrier:
 // items, waits and completion counters are per wave, and the lane that
 // fetches broadcasts the item with readfirstlane.
 
-constexpr uint32_t kSegPollLimit = 1u << 20;  // polls of 1-2 us: about a second
+constexpr uint32_t kSegPollLimit = 1u << 20;  // default: polls of 1-2 us, about a second
+
+// Launch options (rms_set_option): which walk kernel runs and the poll limit
+// of the persistent walk's waits.  Process-wide; read at each launch.
+std::atomic<int> g_walk_choice{RMS_WALK_AUTO};
+std::atomic<uint32_t> g_seg_poll_limit{kSegPollLimit};
 // At least 2048 steps a segment: fewer segment boundaries (each moves the
 // walker states through HBM) against a shorter last segment; at 1e6 walkers x
 // 1e4 steps five segments beat ten by 1.6% (FP64 63.0 against 64.1 ms, mixed
@@ -286,7 +293,8 @@ __global__ __launch_bounds__(kBlock) void seg_init_kernel(uint32_t* ctl, int64_t
 
 template <class Walker, typename LabelT>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(Walker::kWaves, 8))) void walk_seg_kernel(
-    WalkPlan p, uint32_t n_seg, uint32_t seg_steps, uint32_t waves_per_queue) {
+    WalkPlan p, uint32_t n_seg, uint32_t seg_steps, uint32_t waves_per_queue,
+    uint32_t poll_limit) {
     __shared__ double trig[Walker::kTrig ? 2 * kTrigSize : 2];
     load_trig<Walker>(p, trig);  // the only block barrier, before the loop
     const LabelT* __restrict__ lab = static_cast<const LabelT*>(p.labels);
@@ -313,10 +321,10 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(Walker::
         if (seg > 0) {
             uint32_t polls = 0;
             while (__hip_atomic_load(&done[sw], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < seg) {
-                if (++polls > kSegPollLimit) break;
+                if (++polls > poll_limit) break;
                 __builtin_amdgcn_s_sleep(8);
             }
-            if (polls > kSegPollLimit) {
+            if (polls > poll_limit) {
                 if (lane == 0) atomicOr(fail_flag, 1u);
                 break;
             }
@@ -369,15 +377,18 @@ int seg_grid() {
 // all of them do.  Other walks, and walks so long that the item count (slot
 // waves x segments) would pass 2^30, take the one-launch kernel.
 template <template <typename, int> class Walker, typename LabelT, int NS>
-hipError_t run_seg(const WalkPlan& p, hipStream_t s) {
+hipError_t run_seg(const WalkPlan& p, hipStream_t s, int* kind) {
     const int grid_blocks = seg_grid<Walker<LabelT, NS>, LabelT>();
     const uint32_t seg_steps = seg_steps_of(p.n_steps);
     const int64_t n_seg64 = p.n_steps == 0 ? 1 : (p.n_steps + seg_steps - 1) / seg_steps;
     const int64_t wpq64 = p.n_slots / kWave / kSegQueues;
     const int64_t slot_waves = p.n_slots / kWave;
     const int64_t resident = static_cast<int64_t>(grid_blocks) * kWavesPerBlock;
-    const bool persistent = 2 * slot_waves > 3 * resident && 2 * slot_waves <= 9 * resident &&
+    const int choice = g_walk_choice.load(std::memory_order_relaxed);
+    const bool in_window = 2 * slot_waves > 3 * resident && 2 * slot_waves <= 9 * resident;
+    const bool persistent = (choice == RMS_WALK_AUTO ? in_window : choice == RMS_WALK_PERSISTENT) &&
                             wpq64 * n_seg64 <= (int64_t(1) << 30);
+    *kind = persistent ? RMS_WALK_PERSISTENT : RMS_WALK_ONE_LAUNCH;
     // queue heads, failure word and completion counters start at zero; the
     // host reads the failure word after either kernel
     const int64_t n_ctl = kSegCtlFixed + p.n_slots / kWave;
@@ -391,18 +402,19 @@ hipError_t run_seg(const WalkPlan& p, hipStream_t s) {
     const uint32_t n_seg = static_cast<uint32_t>(n_seg64);
     const uint32_t wpq = static_cast<uint32_t>(wpq64);
     walk_seg_kernel<Walker<LabelT, NS>, LabelT>
-        <<<dim3(static_cast<unsigned>(grid_blocks)), kBlock, 0, s>>>(p, n_seg, seg_steps, wpq);
+        <<<dim3(static_cast<unsigned>(grid_blocks)), kBlock, 0, s>>>(
+            p, n_seg, seg_steps, wpq, g_seg_poll_limit.load(std::memory_order_relaxed));
     return hipGetLastError();
 }
 
 template <template <typename, int> class Walker, typename LabelT>
-hipError_t run_seg_ns(const WalkPlan& p, hipStream_t s) {
+hipError_t run_seg_ns(const WalkPlan& p, hipStream_t s, int* kind) {
     switch (p.n_shapes) {
-        case 0: return run_seg<Walker, LabelT, 0>(p, s);
-        case 1: return run_seg<Walker, LabelT, 1>(p, s);
-        case 2: return run_seg<Walker, LabelT, 2>(p, s);
-        case 3: return run_seg<Walker, LabelT, 3>(p, s);
-        case 4: return run_seg<Walker, LabelT, 4>(p, s);
+        case 0: return run_seg<Walker, LabelT, 0>(p, s, kind);
+        case 1: return run_seg<Walker, LabelT, 1>(p, s, kind);
+        case 2: return run_seg<Walker, LabelT, 2>(p, s, kind);
+        case 3: return run_seg<Walker, LabelT, 3>(p, s, kind);
+        case 4: return run_seg<Walker, LabelT, 4>(p, s, kind);
         default: return hipErrorInvalidValue;
     }
 }
@@ -501,17 +513,24 @@ hipError_t launch_order(const WalkPlan& p, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_walk(const WalkPlan& p, int precision, hipStream_t s) {
+void set_walk_choice(int choice) { g_walk_choice.store(choice, std::memory_order_relaxed); }
+
+void set_seg_poll_limit(uint32_t polls) {
+    g_seg_poll_limit.store(polls, std::memory_order_relaxed);
+}
+
+hipError_t launch_walk(const WalkPlan& p, int precision, hipStream_t s, int* kind) {
+    *kind = RMS_WALK_ONE_LAUNCH;
     if (p.n_walkers <= 0) return hipSuccess;
     const bool u8 = p.label_bytes == 1;
     const bool seg = p.order && p.seg_state && p.seg_ctl;
     if (p.thr_mt) {  // absorbing membranes
         if (seg) {
             if (precision == RMS_FP64)
-                return u8 ? run_seg_ns<dev::WalkerF64MT, uint8_t>(p, s)
-                          : run_seg_ns<dev::WalkerF64MT, uint16_t>(p, s);
-            return u8 ? run_seg_ns<dev::WalkerMixedMT, uint8_t>(p, s)
-                      : run_seg_ns<dev::WalkerMixedMT, uint16_t>(p, s);
+                return u8 ? run_seg_ns<dev::WalkerF64MT, uint8_t>(p, s, kind)
+                          : run_seg_ns<dev::WalkerF64MT, uint16_t>(p, s, kind);
+            return u8 ? run_seg_ns<dev::WalkerMixedMT, uint8_t>(p, s, kind)
+                      : run_seg_ns<dev::WalkerMixedMT, uint16_t>(p, s, kind);
         }
         if (precision == RMS_FP64)
             return u8 ? run_ns<dev::WalkerF64MT, uint8_t>(p, s)
@@ -521,10 +540,10 @@ hipError_t launch_walk(const WalkPlan& p, int precision, hipStream_t s) {
     }
     if (seg) {
         if (precision == RMS_FP64)
-            return u8 ? run_seg_ns<dev::WalkerF64, uint8_t>(p, s)
-                      : run_seg_ns<dev::WalkerF64, uint16_t>(p, s);
-        return u8 ? run_seg_ns<dev::WalkerMixed, uint8_t>(p, s)
-                  : run_seg_ns<dev::WalkerMixed, uint16_t>(p, s);
+            return u8 ? run_seg_ns<dev::WalkerF64, uint8_t>(p, s, kind)
+                      : run_seg_ns<dev::WalkerF64, uint16_t>(p, s, kind);
+        return u8 ? run_seg_ns<dev::WalkerMixed, uint8_t>(p, s, kind)
+                  : run_seg_ns<dev::WalkerMixed, uint16_t>(p, s, kind);
     }
     if (precision == RMS_FP64)
         return u8 ? run_ns<dev::WalkerF64, uint8_t>(p, s) : run_ns<dev::WalkerF64, uint16_t>(p, s);

@@ -84,5 +84,5 @@ def test_mixed_permeable_cells():
                  dirs=fibonacci_hemisphere(7), bvals=[0.0, 0.7, 3.0])
     same = _compare(g, o, "cells")
     assert math.isclose(g["sum_alpha"], o["sum_alpha"], rel_tol=1e-5)
-    # R of identical walkers: compensated fp32 sums
+    # R of identical walkers: fp32 time shares accumulated in an fp64 sum
     assert np.allclose(g["dump"][same, 3], o["dump"][same, 3], rtol=1e-6, atol=1e-9)

@@ -48,6 +48,57 @@ def test_bad_substrate_arguments(bad):
     assert e.value.code == -1
 
 
+def test_binding_checks_array_sizes_before_the_library_reads_them():
+    """The library reads n_shapes * n_steps waveform samples and n_labels (or
+    n_labels^2) tissue values through raw pointers: the binding refuses arrays
+    of other sizes before any call."""
+    fake = rms.Substrate(None, (2, 2, 2), 2, 0.1)  # never reaches the library
+    run = dict(seed=1, n_walkers=8, n_steps=10, dt=2e-4, dirs=[[1.0, 0, 0]], bvals=[0.0])
+    with pytest.raises(ValueError, match="waveform"):
+        rms.rms_run(fake, waveform=np.zeros((1, 9)), **run)
+    with pytest.raises(ValueError, match="waveform"):
+        rms.rms_run_record(fake, waveform=np.zeros((2, 11)), record_steps=[5], **run)
+    with pytest.raises(ValueError, match="T2"):
+        rms.rms_run(fake, params=dict(D=[2.0, 2.0], T2=[80.0]), **run)
+    with pytest.raises(ValueError, match="kappa"):
+        rms.rms_run(fake, params=dict(D=[2.0, 2.0], kappa=np.zeros(3)), **run)
+    with pytest.raises(ValueError, match="rho"):
+        rms.rms_run(fake, params=dict(D=[2.0, 2.0], rho=np.zeros((3, 3))), **run)
+    with pytest.raises(ValueError, match="conc"):
+        rms.rms_run(fake, params=dict(D=[2.0, 2.0], conc=[1.0, 1.0, 1.0]), **run)
+    with pytest.raises(ValueError, match="D must have 2"):
+        rms.rms_run(fake, params=dict(D=[2.0, 2.0, 2.0]), **run)
+    with pytest.raises(ValueError, match="dirs"):
+        rms.rms_run(fake, dirs=np.zeros((2, 2)), seed=1, n_walkers=8, n_steps=10, dt=2e-4)
+    lab = np.zeros((2, 2, 2), np.uint8)
+    with pytest.raises(ValueError, match="T2"):
+        rms.rms_create_substrate(lab, 0.1, [2.0, 2.0], None, [80.0])
+    with pytest.raises(ValueError, match="kappa"):
+        rms.rms_create_substrate(lab, 0.1, [2.0, 2.0], np.zeros(2))
+    with pytest.raises(ValueError, match="dead"):
+        rms.rms_create_substrate(lab, 0.1, [2.0, 2.0], dead=[0, 0, 1])
+
+
+def test_set_option_validates_without_a_device():
+    with pytest.raises(rms.RmsError) as e:
+        rms.rms_set_option(99, 0)
+    assert e.value.code == -1
+    with pytest.raises(rms.RmsError):
+        rms.rms_set_option(rms.RMS_OPT_WALK_KERNEL, 7)
+    with pytest.raises(rms.RmsError):
+        rms.rms_set_option(rms.RMS_OPT_SEG_POLL_LIMIT, -1)
+    rms.rms_set_option(rms.RMS_OPT_WALK_KERNEL, rms.RMS_WALK_ONE_LAUNCH)
+    rms.rms_set_option(rms.RMS_OPT_SEG_POLL_LIMIT, 0)
+    rms.rms_set_option(rms.RMS_OPT_WALK_KERNEL, rms.RMS_WALK_AUTO)
+    rms.rms_set_option(rms.RMS_OPT_SEG_POLL_LIMIT, 1 << 20)
+    text = open(os.path.join(ROOT, "include", "rms.h")).read()
+    for name in ("RMS_WALK_ONE_LAUNCH", "RMS_WALK_PERSISTENT", "RMS_WALK_PACKED",
+                 "RMS_OPT_WALK_KERNEL", "RMS_OPT_SEG_POLL_LIMIT"):
+        assert getattr(rms, name) == int(re.search(rf"#define {name} (\d+)", text).group(1))
+    assert rms.ERROR_NAMES[rms.RMS_E_WAIT_GAVE_UP] == "RMS_E_WAIT_GAVE_UP"
+    assert int(re.search(r"#define RMS_E_WAIT_GAVE_UP \((-\d+)\)", text).group(1)) == -10
+
+
 def test_header_limits_match_binding():
     text = open(os.path.join(ROOT, "include", "rms.h")).read()
     for name in ("RMS_MAX_SHAPES", "RMS_MAX_SIGNALS", "RMS_MAX_LABELS", "RMS_DUMP_FIXED"):

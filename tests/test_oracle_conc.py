@@ -51,6 +51,28 @@ def test_baxter_probabilities(D1, D2, c1, c2):
     assert oracle.conc_perm_probs(0.0, D1, D2, c1, c2, 0.0, 1, 2e-4) == (0.0, 0.0)
 
 
+def test_baxter_probability_one_permeates_on_every_word():
+    """Baxter's rule gives probability 1 from the side of smaller c sqrt(D)
+    (Eq. alt-perm-prob1-2): its threshold is 2^32, so even the largest 32-bit
+    membrane word permeates; from the other side the largest word reflects."""
+    D = np.array([1.0, 2.0])
+    conc = np.array([1.0, 1.0])  # c sqrt(D): 1 (label 0) < sqrt 2 (label 1)
+    kap = np.array([[0.0, 0.5], [0.5, 0.0]])
+    thr = oracle.conc_tables(D, kap, None, conc, 0.0, 1, 2e-4)
+    assert int(thr[0, 1]) == 2**32
+    assert int(thr[1, 0]) == math.floor(math.sqrt(0.5) * 2**32)
+    lab = np.zeros((2, 2, 2), np.uint8)
+    lab[:, :, 1] = 1
+    sigma, _, inv = oracle.tables(D, None, None, None, 2e-4, 0.1)
+    top = 2**32 - 1
+    r = oracle.single_step(lab, 0.1, 2e-4, sigma, thr, inv, [0, 0, 0], [0.99, 0.5, 0.5], 0,
+                           [1.0, 0.0, 0.0], (top, 0, 0))
+    assert r["hits"] == 1 and r["perms"] == 1 and r["label"] == 1
+    r = oracle.single_step(lab, 0.1, 2e-4, sigma, thr, inv, [1, 0, 0], [0.01, 0.5, 0.5], 1,
+                           [-1.0, 0.0, 0.0], (top, 0, 0))
+    assert r["hits"] == 1 and r["perms"] == 0 and r["label"] == 1
+
+
 @pytest.mark.parametrize("D1,D2,c1,c2", CASES)
 def test_printed_lambda_and_kappa_correction(D1, D2, c1, c2):
     """alpha_lambda as printed is r^lambda times a constant (r = c2/c1), so on
