@@ -1,15 +1,18 @@
 """Benchmark: walker-steps/s of the MI355X walker on one GPU.
 
 One benchmark step is one rms_run of the whole hot path (start, walk, signal
-and moment reductions, results in host memory) over the permeable ellipsoid
-packing: 200^3 uint16 labels at 0.1 um, 120 cells (D 2 intra / 2.5 extra,
-kappa 0.02 um/ms, T2 80/60 ms), 1e6 walkers x 1e4 steps at dt = 2e-4 ms, PGSE
-(delta 0.5, Delta 1.5 ms), 30 directions x 6 b values.  The substrate is
-resident in HBM before the timed region starts.
+and moment reductions, results in host memory) over the synthetic axon
+bundle: 400x400x1000 uint16 labels at 0.1 um, 300 beaded undulating tubes
+(D 2 intra / 1.8 extra, kappa 0.01 um/ms), 1e7 walkers x 2e4 steps at
+dt = 2e-4 ms, FP64, two gradient shapes (PGSE delta 1 / Delta 3 ms and a
+cosine OGSE), 30 directions x 6 b values.  The substrate is resident in HBM
+before the timed region starts.
 
 Prints one JSON line (see the keys below) with a roofline entry for the walk
-kernel (timed with HIP events on the run's stream) and the CPU oracle timed on
-a bounded sample of the same workload.
+kernel (timed with HIP events on the run's stream), the CPU oracle timed on a
+bounded sample of the same workload (on the host's cores, and on one core),
+and the signal error of the GPU run of the oracle's walker sample against the
+oracle (same seed, walkers 0..N-1).
 """
 from __future__ import annotations
 
@@ -69,19 +72,15 @@ def kernel_sha() -> str:
     return h.hexdigest()[:16]
 
 
-def walk_kernel_name(fp64: bool, c: dict) -> str:
-    """Name of the walk kernel rms_run launches for workload c: the persistent
-    segmented walk (walk_seg_kernel) when the walkers fill between 1.5 and 4.5
-    rounds of resident waves (1024 SIMDs x 5 waves for the FP64 walker, x 6
-    for the mixed one), else the one-launch walk_kernel."""
+def walk_kernel_name(fp64: bool, c: dict, kind: str) -> str:
+    """Template name of the walk kernel a run launched (``kind`` is the
+    library's rms_result.walk_kernel: "persistent" is walk_seg_kernel, "one
+    launch" walk_kernel)."""
     lab = "uint16" if c["labels"].dtype.itemsize == 2 or int(c["labels"].max()) >= 32 else "uint8"
     ns = int(np.asarray(c["waveform"]).reshape(-1, c["n_steps"]).shape[0])
     walker = "WalkerF64T" if fp64 else "WalkerMixedT"
-    spec = f"{walker}<{lab},{ns},false>"
-    rounds = c["n_walkers"] / (1024 * (5 if fp64 else 6) * 64)
-    if 1.5 < rounds <= 4.5:
-        return f"walk_seg_kernel<{spec}> (persistent)"
-    return f"walk_kernel<{spec}> (one launch)"
+    base = "walk_seg_kernel" if kind == "persistent" else "walk_kernel"
+    return f"{base}<{walker}<{lab},{ns},false>> ({kind})"
 
 
 def traffic_from_profile(name: str, precision: str):
@@ -97,19 +96,55 @@ def traffic_from_profile(name: str, precision: str):
     return t.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(c, sample_walkers: int):
+def host_cores() -> int:
+    """CPU cores this process may run on (its affinity set)."""
+    try:
+        return len(os.sched_getaffinity(0))
+    except AttributeError:
+        return os.cpu_count() or 1
+
+
+def cpu_baseline(c, sample_walkers: int, one_core_walkers: int):
+    """The oracle on walkers 0..N-1 of the workload (all steps), on the host's
+    cores (at most 16, the host share of one GPU), then on one core over a
+    smaller sample.  Returns the bench entry and the oracle's result."""
     import oracle
-    threads = min(os.cpu_count() or 1, 16)
+    threads = min(host_cores(), 16)
     n = min(sample_walkers, c["n_walkers"])
+    run = dict(seed=c["seed"], n_steps=c["n_steps"], dt=c["dt"], waveform=c["waveform"],
+               dirs=c["dirs"], bvals=c["bvals"])
+    t0 = time.perf_counter()
+    o = oracle.run(c["labels"], c["voxel_um"], c["D"], c["kappa"], c["T2"], c.get("dead"),
+                   n_walkers=n, n_threads=threads, **run)
+    el = time.perf_counter() - t0
+    n1 = min(one_core_walkers, c["n_walkers"])
     t0 = time.perf_counter()
     oracle.run(c["labels"], c["voxel_um"], c["D"], c["kappa"], c["T2"], c.get("dead"),
-               seed=c["seed"], n_walkers=n, n_steps=c["n_steps"], dt=c["dt"],
-               waveform=c["waveform"], dirs=c["dirs"], bvals=c["bvals"], n_threads=threads)
-    el = time.perf_counter() - t0
-    return {"value": n * c["n_steps"] / el, "unit": "walker-steps/s", "cores": threads,
-            "kind": "oracle",
-            "sample": f"walkers 0..{n - 1} of the same run (all {c['n_steps']} steps), "
-                      f"{el:.1f} s on {threads} threads"}
+               n_walkers=n1, n_threads=1, **run)
+    el1 = time.perf_counter() - t0
+    entry = {"value": n * c["n_steps"] / el, "unit": "walker-steps/s", "cores": threads,
+             "kind": "oracle",
+             "sample": f"walkers 0..{n - 1} of the same run (all {c['n_steps']} steps), "
+                       f"{el:.1f} s on {threads} threads",
+             "cores_available": host_cores(),
+             "value_1core": n1 * c["n_steps"] / el1,
+             "sample_1core": f"walkers 0..{n1 - 1} (all steps), {el1:.1f} s on 1 thread"}
+    return entry, o
+
+
+def signal_error(rms, sub, c, o, prec, stream) -> dict:
+    """The GPU run of the oracle's walker sample (same seed: walkers 0..N-1)
+    against the oracle: max |S - S_oracle| over shapes, b values and
+    directions, and the relative error of the moments."""
+    n = int(o["n_walkers"])
+    g = rms.rms_run(sub, seed=c["seed"], n_walkers=n, n_steps=c["n_steps"], dt=c["dt"],
+                    waveform=c["waveform"], dirs=c["dirs"], bvals=c["bvals"], precision=prec,
+                    stream=stream)
+    rel = lambda a, b: float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+    return {"n_walkers": n,
+            "max_abs_signal_err": float(np.max(np.abs(g["signal"] - o["signal"]))),
+            "m2_rel_err": rel(g["m2"], o["m2"]), "m4_rel_err": rel(g["m4"], o["m4"]),
+            "sum_alpha_rel_err": abs(g["sum_alpha"] - o["sum_alpha"]) / o["sum_alpha"]}
 
 
 def served_substrates():
@@ -465,10 +500,11 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--precision", choices=("fp64", "mixed"), default="fp64")
-    ap.add_argument("--workload", choices=WORKLOADS, default="ellipsoids200")
+    ap.add_argument("--workload", choices=WORKLOADS, default="axons")
     ap.add_argument("--walkers", type=int, default=0,
                     help="walker count in place of the workload's (the plain benchmark only)")
     ap.add_argument("--cpu-sample-walkers", type=int, default=250_000)
+    ap.add_argument("--cpu-1core-walkers", type=int, default=2_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--precision-report", action="store_true",
                     help="mixed vs fp64 on the same inputs: error per b, direction, moment")
@@ -583,14 +619,21 @@ def main():
                      "unit": "TOP/s", "frac": achieved / VALU_PEAK_TOPS,
                      "traffic": (traffic_from_profile(c["name"], args.precision)
                                  if c["n_walkers"] == default_walkers else None),
-                     "kernel": walk_kernel_name(prec == rms.RMS_FP64, c),
+                     "kernel": walk_kernel_name(prec == rms.RMS_FP64, c, r["walk_kernel"]),
                      "kernel_ms": kernel_s * 1e3, "ops_per_walker_step": OPS_TOTAL},
         "last_signal_b_max_dir0": [float(r["signal"][0, -1, 0].real),
                                    float(r["signal"][0, -1, 0].imag)],
     }
     if not args.no_cpu_baseline:
-        log(f"[bench] timing the CPU oracle on {args.cpu_sample_walkers} walkers")
-        line["cpu_baseline"] = cpu_baseline(c, args.cpu_sample_walkers)
+        log(f"[bench] timing the CPU oracle on {args.cpu_sample_walkers} walkers "
+            f"({min(host_cores(), 16)} threads) and {args.cpu_1core_walkers} walkers (1 thread)")
+        line["cpu_baseline"], o = cpu_baseline(c, args.cpu_sample_walkers, args.cpu_1core_walkers)
+        o["n_walkers"] = min(args.cpu_sample_walkers, c["n_walkers"])
+        sub = rms.rms_create_substrate(c["labels"], c["voxel_um"], c["D"], c["kappa"], c["T2"],
+                                       c.get("dead"))
+        line["signal_err_vs_oracle"] = signal_error(rms, sub, c, o, prec, stream)
+        sub.close()
+        log(f"[bench] signal error vs oracle: {line['signal_err_vs_oracle']}")
     print(json.dumps(line), flush=True)
 
 

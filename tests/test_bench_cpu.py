@@ -24,16 +24,20 @@ def _case(n_walkers, n_shapes=1, dtype=np.uint16):
                 waveform=np.zeros((n_shapes, 10)))
 
 
-def test_walk_kernel_name_follows_the_launch_rule():
-    # persistent between 1.5 and 4.5 rounds of resident waves (5 x 1024 waves
-    # of 64 lanes FP64, 6 x 1024 mixed), one launch elsewhere
-    assert "walk_seg_kernel" in bench.walk_kernel_name(True, _case(1_000_000))
-    assert "walk_kernel<" in bench.walk_kernel_name(True, _case(400_000))
-    assert "walk_kernel<" in bench.walk_kernel_name(True, _case(3_000_000))
-    assert "walk_seg_kernel" in bench.walk_kernel_name(False, _case(700_000))
-    assert "walk_kernel<" in bench.walk_kernel_name(False, _case(10_000_000, 2))
-    assert "<uint16,2,false>" in bench.walk_kernel_name(False, _case(10_000_000, 2))
-    assert "<uint8,1,false>" in bench.walk_kernel_name(True, _case(10_000, 1, np.uint8))
+def test_walk_kernel_name_takes_the_kind_the_library_reports():
+    assert bench.walk_kernel_name(True, _case(1_000_000), "persistent").startswith(
+        "walk_seg_kernel<WalkerF64T<uint16,1,false>>")
+    assert bench.walk_kernel_name(True, _case(10_000, 1, np.uint8), "one launch") == (
+        "walk_kernel<WalkerF64T<uint8,1,false>> (one launch)")
+    assert "<uint16,2,false>" in bench.walk_kernel_name(False, _case(10_000_000, 2),
+                                                        "one launch")
+
+
+def test_default_workload_is_the_axon_bundle():
+    src = open(os.path.join(ROOT, "bench.py")).read()
+    assert 'choices=WORKLOADS, default="axons"' in src
+    c = bench.WORKLOADS
+    assert "axons" in c
 
 
 def test_traffic_needs_the_profiled_sources():
@@ -41,5 +45,5 @@ def test_traffic_needs_the_profiled_sources():
     value recorded with the counters."""
     sha = bench.kernel_sha()
     assert len(sha) == 16 and int(sha, 16) >= 0
-    t = bench.traffic_from_profile("ellipsoids200_u16", "fp64")
+    t = bench.traffic_from_profile("axons400x400x1000_u16", "fp64")
     assert t is None or t > 0
