@@ -219,6 +219,16 @@ DUMP_FIELDS = ["dx", "dy", "dz", "R", "label", "ix", "iy", "iz", "ox", "oy", "oz
                "label0", "n_face", "n_hit", "n_perm"]
 
 
+def host_threads() -> int:
+    """Worker threads for the oracle: the cores this process may run on, at
+    most 16 (the host share of one GPU on the measurement machines)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(n, 16))
+
+
 def run(labels, voxel_um, D, kappa=None, T2=None, dead=None, *, seed, n_walkers, n_steps, dt,
         waveform=None, dirs=None, bvals=None, walker_ids=None, n_threads=None, dump=False,
         rec_steps=None, rho=None, conc=None, lam=0.0, perm_model=0):
@@ -270,7 +280,7 @@ def run(labels, voxel_um, D, kappa=None, T2=None, dead=None, *, seed, n_walkers,
     nr = 0 if rs is None else rs.size
     ro = np.zeros(max(nr, 1) * (22 + 2 * nd))
     if n_threads is None:
-        n_threads = os.cpu_count() or 1
+        n_threads = host_threads()
     rc = lib.rmso_run(lab.ctypes.data, lab.dtype.itemsize, _ptr(dims, C.c_int64), voxel_um, n,
                       _ptr(D, C.c_double), _ptr(kap, C.c_double), _ptr(t2, C.c_double),
                       _ptr(dd, C.c_uint8), int(seed) & (2**64 - 1), int(n_walkers),

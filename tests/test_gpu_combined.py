@@ -20,7 +20,7 @@ from rms_inputs import ellipsoid_packing, six_dirs, pgse
 
 pytestmark = pytest.mark.gpu
 
-NT = os.cpu_count() or 4
+NT = oracle.host_threads()
 
 
 @pytest.fixture(scope="module", autouse=True)

@@ -19,7 +19,7 @@ from rms_inputs import cylinder_z, six_dirs
 
 pytestmark = pytest.mark.gpu
 
-NT = os.cpu_count() or 4
+NT = oracle.host_threads()
 
 
 @pytest.fixture(scope="module", autouse=True)

@@ -15,7 +15,7 @@ from rms_inputs import configs
 
 pytestmark = pytest.mark.gpu
 
-NT = os.cpu_count() or 4
+NT = oracle.host_threads()
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -79,7 +79,46 @@ def test_spin_concentrations_full_size_sampled():
     assert abs(np.mean(d[:, 4] > 0) - want) < 4 * se * math.sqrt(2)
 
 
-def test_axon_bundle_recorded_moments_and_fits():
+@pytest.fixture(scope="module")
+def axons():
+    return configs.axon_case()
+
+
+def test_axon_bundle_precision_form_error(axons):
+    """The precision form on the axon bundle at full size (1e7 walkers x 2e4
+    steps, PGSE and OGSE, 30 directions x 6 b): against the FP64 form (which
+    matches the oracle walker by walker) every signal, per shape, b value and
+    direction, lies within 1e-3, and so do the moments (relative) and D and K
+    per direction; on the first 20000 walkers the mixed form is within 1e-3 of
+    the oracle itself."""
+    c = axons
+    sub = rms.rms_create_substrate(c["labels"], c["voxel_um"], c["D"], c["kappa"], c["T2"])
+    kw = dict(seed=c["seed"], n_steps=c["n_steps"], dt=c["dt"], waveform=c["waveform"],
+              dirs=c["dirs"], bvals=c["bvals"])
+    print("[case] axons full size, fp64 and mixed", flush=True)
+    a = rms.rms_run(sub, n_walkers=c["n_walkers"], precision=rms.RMS_FP64, **kw)
+    b = rms.rms_run(sub, n_walkers=c["n_walkers"], precision=rms.RMS_MIXED, **kw)
+    n = 20_000
+    m = rms.rms_run(sub, n_walkers=n, precision=rms.RMS_MIXED, **kw)
+    sub.close()
+    dS = np.abs(a["signal"] - b["signal"])  # [shape][b][direction]
+    print(f"mixed vs fp64: max |dS| {dS.max():.2e}, per b {dS.max(axis=(0, 2))}", flush=True)
+    assert dS.max() <= 1e-3
+    for k in ("m2", "m4"):
+        rel = np.abs(a[k] - b[k]) / np.max(np.abs(a[k]))
+        print(f"{k} relative error {rel.max():.2e}", flush=True)
+        assert rel.max() <= 1e-3
+    assert np.max(np.abs(a["D"] - b["D"]) / a["D"]) <= 1e-3
+    assert np.max(np.abs(a["K"] - b["K"])) <= 1e-3
+    o = oracle.run(c["labels"], c["voxel_um"], c["D"], c["kappa"], c["T2"], n_walkers=n,
+                   n_threads=NT, **kw)
+    dO = np.max(np.abs(m["signal"] - o["signal"]))
+    print(f"mixed vs oracle, {n} walkers: max |dS| {dO:.2e}", flush=True)
+    assert dO <= 1e-3
+    assert np.max(np.abs(m["m2"] - o["m2"]) / np.max(np.abs(o["m2"]))) <= 1e-3
+
+
+def test_axon_bundle_recorded_moments_and_fits(axons):
     """The 400 x 400 x 1000 beaded-axon bundle at full size (1e7 walkers x 2e4
     steps, mixed form) with moments recorded every 1000 steps: the end results
     equal rms_run's bit for bit; along the bundle (its axes run near z)
@@ -90,7 +129,7 @@ def test_axon_bundle_recorded_moments_and_fits():
     b = 0 and falls with b, and the cumulant fit (b <= 1) gives a larger D
     along the bundle than across it, all positive and not above D0 (within 2%
     for the fit)."""
-    c = configs.axon_case()
+    c = axons
     prec = rms.RMS_MIXED
     steps = np.arange(1000, c["n_steps"] + 1, 1000)
     kw = dict(seed=c["seed"], n_walkers=c["n_walkers"], n_steps=c["n_steps"], dt=c["dt"],

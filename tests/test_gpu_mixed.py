@@ -19,7 +19,7 @@ import paper_2012_06478_amd as rms
 from rms_inputs import cylinder_z, ellipsoid_packing, pgse, fibonacci_hemisphere, configs
 
 pytestmark = pytest.mark.gpu
-NT = os.cpu_count() or 4
+NT = oracle.host_threads()
 
 
 @pytest.fixture(scope="module", autouse=True)

@@ -20,7 +20,7 @@ from rms_inputs import (uniform_volume, cylinder_z, slab_x, ellipsoid_packing, p
 
 pytestmark = pytest.mark.gpu
 
-NT = os.cpu_count() or 4
+NT = oracle.host_threads()
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -262,6 +262,33 @@ def test_ellipsoid_config_full_size_sampled():
     assert g["n_permeations"] == int(dump[:, 14].sum())
     assert g["n_membrane_hits"] == int(dump[:, 13].sum())
     assert 0 < g["max_perm_prob"] < 0.01
+
+
+def test_ellipsoid_full_walker_count_whole_result_against_oracle():
+    """The 200^3 packing with its full 1e6 walkers for 4096 steps: the launch
+    takes the persistent walk (two segments) and the final reduction more than
+    256 blocks.  Every walker matches the oracle's, and so does the whole
+    result: all 180 signals, the moments, D and K per direction."""
+    c = configs.ellipsoid_case(n_steps=4096)
+    sub = rms.rms_create_substrate(c["labels"], c["voxel_um"], c["D"], c["kappa"], c["T2"])
+    print("[case] ellipsoids 200^3, 1e6 walkers x 4096 steps, whole result", flush=True)
+    run = dict(seed=c["seed"], n_walkers=c["n_walkers"], n_steps=c["n_steps"], dt=c["dt"],
+               waveform=c["waveform"], dirs=c["dirs"], bvals=c["bvals"], dump=True)
+    g = rms.rms_run(sub, **run)
+    sub.close()
+    assert g["walk_kernel"] == "persistent"
+    o = oracle.run(c["labels"], c["voxel_um"], c["D"], c["kappa"], c["T2"], n_threads=NT, **run)
+    _assert_walkers(g, o, 1e-9)
+    dS = np.max(np.abs(g["signal"] - o["signal"]))
+    print(f"max |S - S_oracle| {dS:.3e}", flush=True)
+    assert dS <= 1e-9
+    assert np.allclose(g["m2"], o["m2"], rtol=1e-10, atol=0)
+    assert np.allclose(g["m4"], o["m4"], rtol=1e-10, atol=1e-30)
+    assert np.allclose(g["D"], o["D"], rtol=1e-10)
+    assert np.allclose(g["K"], o["K"], rtol=1e-8, atol=1e-12)
+    assert math.isclose(g["sum_alpha"], o["sum_alpha"], rel_tol=1e-12)
+    for k in ("n_face_events", "n_membrane_hits", "n_permeations"):
+        assert g[k] == o[k], k
 
 
 def test_b0_exactly_one_and_free_pins_on_gpu():

@@ -10,6 +10,7 @@ import time
 import numpy as np
 import pytest
 
+import oracle
 import paper_2012_06478_amd as rms
 from rms_inputs import cylinder_z, ellipsoid_packing, pgse, six_dirs, fibonacci_hemisphere
 
@@ -82,6 +83,50 @@ def test_server_matches_rms_run(substrates):
         ref = rms.rms_run(s, **kw)
         _same(got, ref)
         assert got["wall_s"] >= got["queue_s"] >= 0.0
+
+
+def test_served_requests_match_the_oracle(substrates):
+    """An FP64 and a mixed-precision request served together with a third one,
+    each against the oracle on the same inputs: FP64 summaries within 1e-9
+    (signals) and 1e-10 (moments, relative) with equal event counts; the mixed
+    form's signals within 1e-3."""
+    lab, _ = ellipsoid_packing(n=48, n_cells=12, semi_um=(0.6, 1.4), seed=9)
+    L = int(lab.max()) + 1
+    D = np.full(L, 2.0)
+    D[0] = 2.5
+    kap = np.zeros((L, L))
+    kap[0, 1:] = kap[1:, 0] = 0.2
+    T2 = np.full(L, 80.0)
+    T2[0] = 60.0
+    n, dt = 1500, 2e-4
+    base = dict(n_walkers=20_000, n_steps=n, dt=dt, waveform=pgse(n, dt, 0.05, 0.2),
+                dirs=fibonacci_hemisphere(9), bvals=[0.0, 0.5, 1.0, 2.5])
+    reqs = [dict(seed=31, precision=rms.RMS_FP64, **base),
+            dict(seed=32, precision=rms.RMS_MIXED, **base)]
+    srv = rms.rms_server_create(0, 400)
+    try:
+        print("[case] served requests vs oracle", flush=True)
+        other = rms.rms_server_submit(srv, substrates["cyl"], seed=3, n_walkers=5000,
+                                      n_steps=1000, dt=dt, dirs=six_dirs())
+        tickets = [rms.rms_server_submit(srv, substrates["cells"], **q) for q in reqs]
+        got = [rms.rms_server_wait(srv, t, sh) for t, sh in tickets]
+        rms.rms_server_wait(srv, *other)
+    finally:
+        rms.rms_server_destroy(srv)
+    for q, g in zip(reqs, got):
+        kw = {k: v for k, v in q.items() if k != "precision"}
+        o = oracle.run(lab, 0.1, D, kap, T2, n_threads=oracle.host_threads(), **kw)
+        dS = np.max(np.abs(g["signal"] - o["signal"]))
+        rel2 = np.max(np.abs(g["m2"] - o["m2"])) / np.max(np.abs(o["m2"]))
+        print(f"precision {q['precision']}: max |dS| {dS:.2e}, M2 rel {rel2:.2e}", flush=True)
+        if q["precision"] == rms.RMS_FP64:
+            assert dS <= 1e-9 and rel2 <= 1e-10
+            assert np.max(np.abs(g["m4"] - o["m4"])) <= 1e-10 * np.max(np.abs(o["m4"]))
+            assert abs(g["sum_alpha"] - o["sum_alpha"]) <= 1e-12 * o["sum_alpha"]
+            for k in ("n_face_events", "n_membrane_hits", "n_permeations"):
+                assert g[k] == o[k], k
+        else:
+            assert dS <= 1e-3 and rel2 <= 1e-3
 
 
 def test_alone_equals_in_mix(substrates):

@@ -28,7 +28,7 @@ import pytest
 import oracle
 from rms_inputs import cylinder_z, six_dirs
 
-NT = os.cpu_count() or 4
+NT = oracle.host_threads()
 C3 = 2.0 / 3.0
 
 

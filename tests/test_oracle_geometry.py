@@ -27,7 +27,7 @@ import numpy as np
 import oracle
 from rms_inputs import cube_cell, sphere_cell, six_dirs
 
-NT = os.cpu_count() or 4
+NT = oracle.host_threads()
 LP = 0.1  # voxel size, um
 
 

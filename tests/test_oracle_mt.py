@@ -25,7 +25,7 @@ from scipy.optimize import brentq
 import oracle
 from rms_inputs import cylinder_z, six_dirs
 
-NT = os.cpu_count() or 4
+NT = oracle.host_threads()
 
 
 def test_mt_probability_uses_perm_prob_constant():

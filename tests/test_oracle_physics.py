@@ -16,7 +16,7 @@ from scipy.stats import chi2
 import oracle
 from rms_inputs import uniform_volume, cylinder_z, slab_x, pgse, six_dirs
 
-NT = os.cpu_count() or 4
+NT = oracle.host_threads()
 INF = float("inf")
 
 

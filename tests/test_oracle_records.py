@@ -21,7 +21,7 @@ import pytest
 import oracle
 from rms_inputs import cylinder_z, uniform_volume, six_dirs
 
-NT = os.cpu_count() or 4
+NT = oracle.host_threads()
 
 
 def _run(labels, D, *, kappa=None, T2=None, n_walkers, n_steps, dt=2e-4, rec_steps=None,
