@@ -280,6 +280,162 @@ def test_exchange_matches_diffusion_with_genuine_kappa(D_in, D_out):
         assert abs(f - f_ref) < 4 * se + 0.002, (s, f, f_ref)
 
 
+def test_genuine_kappa_not_input_kappa_at_large_alpha():
+    """Appendix C.1: the input kappa_0 of Eq. (perm-prob) yields the larger
+    genuine permeability kappa = kappa_0 / (1 - alpha) (Eq. kappa-correction),
+    alpha the mean permeation probability of the two sides (Eq.
+    kappa-factor-prob); Eq. (perm-prob-general) is built so that the walk
+    shows the kappa given.  With ds = 0.9 voxel and kappa such that P = 0.2,
+    the share of the slab's walkers still in it follows the diffusion
+    equation with kappa, and not with kappa_0 = (1 - alpha) kappa (outside
+    the same tolerance at the first three times)."""
+    D, sig = 0.5, 0.9
+    ds = sig * 0.1
+    dt = ds * ds / (6 * D)
+    x = 0.25  # kappa ds C_3 / D; P = x / (1 + x) = 0.2 = alpha for equal D
+    kappa = x * D / (ds * 2.0 / 3.0)
+    alpha = x / (1 + x)
+    N = 200_000
+    lab = slab_x(20, 1, 1, 5, 15)
+    k = np.array([[0, kappa], [kappa, 0]])
+    steps = (20, 60, 150, 400)
+    times = [s * dt for s in steps]
+    ref = _fd_tagged_fraction(2.0, 0.5, 1.5, D, D, kappa, times)
+    ref0 = _fd_tagged_fraction(2.0, 0.5, 1.5, D, D, (1 - alpha) * kappa, times)
+    for i, (s, f_ref, f_ref0) in enumerate(zip(steps, ref, ref0)):
+        r = _run(lab, [D, D], kappa=k, n_walkers=N, n_steps=s, dt=dt)
+        assert abs(r["n_permeations"] / r["n_membrane_hits"] - alpha) < 0.01
+        tag = r["dump"][:, 11] == 1
+        f = np.mean(r["dump"][tag, 4] == 1)
+        tol = 4 * math.sqrt(f * (1 - f) / tag.sum()) + 0.002
+        assert abs(f - f_ref) < tol, (s, f, f_ref)
+        if i < 3:  # and the walk is not the diffusion with kappa_0
+            assert abs(f - f_ref0) > tol, (s, f, f_ref0)
+
+
+def test_paper_permeability_validation_delta_source():
+    """Appendix B, the elastic-collision permeability check: two planes at
+    +-a/2 (a = 1 um), kappa = 0.1 um/ms, D_0 = 0.5 um^2/ms on both sides,
+    dt = 4e-4 ms, walkers released at the middle (here: the walkers whose
+    start lies within 0.1 um of it, picked from a uniform start by a run of 0
+    steps), 1000 steps.  The permeability recovered from the density, as the
+    kappa for which the diffusion equation with the membrane condition
+    -D drho/dx = kappa (rho- - rho+) puts the same share of the walkers past
+    the planes at 0.2 and 0.4 ms, lies within 3% of the kappa put in."""
+    from scipy.optimize import brentq
+    D, dt, kappa = 0.5, 4e-4, 0.1
+    lab = slab_x(20, 1, 1, 5, 15)  # planes at x = 0.5 and 1.5 um, middle at 1.0
+    k = np.array([[0, kappa], [kappa, 0]])
+    ids = []
+    for c in range(4):
+        cand = np.arange(c * 1_000_000, (c + 1) * 1_000_000, dtype=np.int64)
+        r = oracle.run(lab, 0.1, [D, D], k, seed=11, walker_ids=cand, n_walkers=cand.size,
+                       n_steps=0, dt=dt, dump=True, n_threads=NT)
+        x0 = (r["dump"][:, 5] + r["dump"][:, 8]) * 0.1
+        ids.append(cand[np.abs(x0 - 1.0) < 0.1])
+    ids = np.concatenate(ids)
+    assert ids.size > 350_000
+
+    h, L = 0.005, 2.0
+    m = int(round(L / h))
+    xc = (np.arange(m) + 0.5) * h
+    inside = (xc >= 0.5) & (xc < 1.5)
+    rho0 = (np.abs(xc - 1.0) < 0.1).astype(float)
+    rho0 /= rho0.sum()
+
+    def outside_share(kap, t):
+        A = np.zeros((m, m))
+        for i in range(m):
+            j = (i + 1) % m
+            c = D / h if inside[i] == inside[j] else 1.0 / (h / D + 1.0 / kap)
+            A[i, i] -= c / h
+            A[i, j] += c / h
+            A[j, j] -= c / h
+            A[j, i] += c / h
+        return (expm(A * t) @ rho0)[~inside].sum()
+
+    for n in (500, 1000):
+        r = oracle.run(lab, 0.1, [D, D], k, seed=11, walker_ids=ids, n_walkers=ids.size,
+                       n_steps=n, dt=dt, dump=True, n_threads=NT)
+        F = np.mean(r["dump"][:, 4] == 0)
+        k_hat = brentq(lambda kk: outside_share(kk, n * dt) - F, 0.02, 0.5)
+        assert abs(k_hat - kappa) < 0.03 * kappa, (n, F, k_hat)
+
+
+def _fd_signal_closed_pore(edges, Ds, kappa, intervals, h=0.005):
+    """Independent reference for the complex signal: the pore [edges[0],
+    edges[-1]) on a line, compartments between successive edges with
+    diffusivities Ds, permeability kappa between neighbouring compartments
+    and reflecting ends, discretised by finite volumes and solved exactly in
+    time.  intervals is a list of (duration, q): during each, every move by
+    dx carries the factor exp(-i q dx), so that a walker's weight is
+    exp(-i sum_k q_k (x(t_k) - x(t_k-1))) (the multiple-propagator form of
+    S = <exp(-i phi)>, section 2.3, Eq. signal); the start is uniform."""
+    L = edges[-1] - edges[0]
+    m = int(round(L / h))
+    xc = edges[0] + (np.arange(m) + 0.5) * h
+    comp = np.searchsorted(edges, xc, side="right") - 1
+    Dc = np.asarray(Ds, float)[comp]
+    rho = np.full(m, 1.0 / m, complex)
+    for dur, q in intervals:
+        A = np.zeros((m, m), complex)
+        for i in range(m - 1):
+            j = i + 1
+            if comp[i] == comp[j]:
+                c = Dc[i] / h
+            else:
+                c = 1.0 / (h / (2 * Dc[i]) + 1.0 / kappa + h / (2 * Dc[j]))
+            A[i, i] -= c / h
+            A[j, i] += c / h * np.exp(-1j * q * h)
+            A[j, j] -= c / h
+            A[i, j] += c / h * np.exp(1j * q * h)
+        rho = expm(A * dur) @ rho
+    return rho.sum()
+
+
+def test_imaginary_signal_sign_multiple_propagator():
+    """The sign convention S = <alpha exp(-i phi)> (section 2.3, Eq. signal),
+    which only the imaginary part shows.  Im S vanishes when the pore is
+    mirror-symmetric or the waveform odd under time reversal, so the pore here
+    is a closed 1 um channel along x with two compartments (0.4 um at D = 2,
+    0.6 um at D = 0.3 um^2/ms, kappa = 2 um/ms between them, dead walls), and
+    the gradient three narrow pulses +1, -3, +2 at steps 1, 1501 and 2001.
+    The phase is then -Q_1 (x_1501 - x_1) + Q_2 (x_2001 - x_1501) along x;
+    the finite-volume multiple-propagator solution of the same problem gives
+    S, imaginary part included; its conjugate, the other sign convention, is
+    excluded by more than twice the tolerance."""
+    dt, N = 2e-4, 200_000
+    n1, n2, n3 = 1, 1501, 2001
+    lab = np.zeros((1, 1, 11), np.uint8)
+    lab[0, 0, 1:5] = 1   # x in [0.1, 0.5) um
+    lab[0, 0, 5:11] = 2  # x in [0.5, 1.1) um
+    D = np.array([1.0, 2.0, 0.3])
+    kap = np.zeros((3, 3))
+    kap[1, 2] = kap[2, 1] = 2.0
+    dead = np.array([1, 0, 0], np.uint8)
+    G = np.zeros(n3)
+    G[n1 - 1], G[n2 - 1], G[n3 - 1] = 1.0, -3.0, 2.0
+    Q = dt * np.cumsum(G[::-1])[::-1]
+    b_unit = dt * np.sum(Q ** 2)
+    for c in (2.0, 3.0):  # phase per um of displacement in the first interval
+        scale = c / dt
+        r = _run(lab, D, kappa=kap, dead=dead, n_walkers=N, n_steps=n3, dt=dt,
+                 waveform=G[None], dirs=np.array([[1.0, 0.0, 0.0]]), bvals=[scale ** 2 * b_unit])
+        phi = scale * r["phase"][:, 0, 0]
+        w = np.exp(-1j * phi)
+        se_re = w.real.std() / math.sqrt(N)
+        se_im = w.imag.std() / math.sqrt(N)
+        S_mc = r["signal"][0, 0, 0]
+        assert abs(S_mc - w.mean()) < 1e-12
+        S_ref = _fd_signal_closed_pore([0.1, 0.5, 1.1], [2.0, 0.3], 2.0,
+                                       [((n2 - n1) * dt, -c), ((n3 - n2) * dt, 2 * c)])
+        tol_im = 4 * se_im + 0.003
+        assert abs(S_mc.real - S_ref.real) < 4 * se_re + 0.003, (c, S_mc, S_ref)
+        assert abs(S_mc.imag - S_ref.imag) < tol_im, (c, S_mc, S_ref)
+        # the other sign convention, <alpha exp(+i phi)>, misses by more than twice that
+        assert abs(S_mc.imag + S_ref.imag) > 2 * tol_im, (c, S_mc, S_ref)
+
+
 def test_t2_time_split_with_exchange():
     """Eq. (wt-relax) with exchange: R = sum_c t_c / T2_c, where t_c is the
     time spent in compartment c.  At equilibrium the expected share of time
