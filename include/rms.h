@@ -251,6 +251,27 @@ int rms_run(const rms_substrate* sub, const rms_params* params, uint64_t seed, i
             const double* dirs, int n_b, const double* bvals, int precision, void* hip_stream,
             rms_result* out);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): rms_run
+ * with every device buffer of the run in a scratch array of the library,
+ * RMS_NOALLOC_MAX_BYTES on each GPU it runs on, held until the process ends.
+ * Arguments, results and errors are those of rms_run, and so are the
+ * kernels: the results equal rms_run's bit for bit.  It calls no device
+ * allocation routine (the array's address and two timing events are set up
+ * at the first call on a device).  A run whose buffers need more than
+ * RMS_NOALLOC_MAX_BYTES (the double-precision form with one gradient shape
+ * and 180 signals fits about 900 000 walkers; the dump buffer of a run is
+ * per-walker records, 8 (15 + 3 n_shapes) bytes a walker) is refused with
+ * RMS_E_INVALID_ARG before any device work.  Every call on one GPU uses the
+ * same array: calls that overlap in time on one GPU (from several threads, or
+ * on several streams) race and give wrong results; calls one after another
+ * are safe, as each run clears whatever it needs cleared. */
+#define RMS_NOALLOC_MAX_BYTES (256ull * 1024ull * 1024ull)
+int rms_run_noalloc(const rms_substrate* sub, const rms_params* params, uint64_t seed,
+                    int64_t n_walkers, int64_t n_steps, double dt_ms, int n_shapes,
+                    const double* waveform, int n_dirs, const double* dirs, int n_b,
+                    const double* bvals, int precision, void* hip_stream, rms_result* out);
+
 /* Displacement moments recorded during a walk: the time dependence of D and
  * K (section 2.3 defines both from the moments of the displacement over the
  * diffusion time t).  After step steps[r] (t = steps[r] dt) each walker is

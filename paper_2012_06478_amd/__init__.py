@@ -29,6 +29,7 @@ RMS_MAX_SIGNALS = 960
 RMS_MAX_LABELS = 4096
 RMS_MAX_PERM_PROB = 0.1
 RMS_DUMP_FIXED = 15
+RMS_NOALLOC_MAX_BYTES = 256 * 1024 * 1024  # scratch array of rms_run_noalloc, per GPU
 RMS_WALK_AUTO = -1
 RMS_WALK_ONE_LAUNCH = 0
 RMS_WALK_PERSISTENT = 1
@@ -122,6 +123,8 @@ def _load():
                             C.c_double, C.c_int, dp, C.c_int, dp, C.c_int, dp, C.c_int,
                             C.c_void_p, C.POINTER(_Result)]
     lib.rms_run.restype = C.c_int
+    lib.rms_run_noalloc.argtypes = lib.rms_run.argtypes
+    lib.rms_run_noalloc.restype = C.c_int
     lib.rms_run_record.argtypes = [C.c_void_p, C.POINTER(_Params), C.c_uint64, C.c_int64,
                                    C.c_int64, C.c_double, C.c_int, dp, C.c_int, dp, C.c_int, dp,
                                    C.c_int, C.c_void_p, C.POINTER(_Record), C.POINTER(_Result)]
@@ -150,7 +153,8 @@ def exported_symbols() -> list[str]:
     """Names the library exports through the C ABI (for load checks)."""
     lib = _load()
     names = ["rms_abi_version", "rms_last_error", "rms_set_option", "rms_create_substrate",
-             "rms_destroy_substrate", "rms_run", "rms_run_record", "rms_spherical_mean",
+             "rms_destroy_substrate", "rms_run", "rms_run_noalloc", "rms_run_record",
+             "rms_spherical_mean",
              "rms_cumulant_fit", "rms_server_create", "rms_server_submit",
              "rms_server_poll", "rms_server_wait", "rms_server_stats_get", "rms_server_destroy"]
     return [n for n in names if hasattr(lib, n)]
@@ -317,17 +321,31 @@ def rms_run(sub: Substrate, *, seed, n_walkers, n_steps, dt, waveform=None, dirs
     absorbing (magnetization transfer), and ``conc`` [n], ``lam``,
     ``perm_model`` for unequal spin concentrations (App. C).  ``stream``: a torch.cuda.Stream or a raw
     hipStream_t (int); None runs on the null stream."""
-    lib = _load()
+    return _run_call(_load().rms_run, sub, seed, n_walkers, n_steps, dt, waveform, dirs, bvals,
+                     precision, params, stream, dump)
+
+
+def rms_run_noalloc(sub: Substrate, *, seed, n_walkers, n_steps, dt, waveform=None, dirs=None,
+                    bvals=None, precision=RMS_FP64, params=None, stream=None,
+                    dump=False) -> dict:
+    """``rms_run`` on the library's device scratch array (no device
+    allocation; runs up to ``RMS_NOALLOC_MAX_BYTES`` of buffers, and calls
+    that overlap on one GPU race; see ``include/rms.h``)."""
+    return _run_call(_load().rms_run_noalloc, sub, seed, n_walkers, n_steps, dt, waveform, dirs,
+                     bvals, precision, params, stream, dump)
+
+
+def _run_call(fn, sub, seed, n_walkers, n_steps, dt, waveform, dirs, bvals, precision, params,
+              stream, dump) -> dict:
     W, g, b = _protocol(n_steps, waveform, dirs, bvals)
     keep = []
     pp = _params(params, keep, sub.n_labels)
     rb = _ResultBuffers(W.shape[0], b.size, g.shape[0])
     wd = np.zeros((int(n_walkers), RMS_DUMP_FIXED + 3 * W.shape[0])) if dump else None
     rb.res.walker_dump = _dptr(wd) if wd is not None else None
-    rc = lib.rms_run(sub.handle, None if pp is None else C.byref(pp), int(seed) & (2**64 - 1),
-                     int(n_walkers), int(n_steps), float(dt), W.shape[0], _dptr(W), g.shape[0],
-                     _dptr(g), b.size, _dptr(b), int(precision), _stream_handle(stream),
-                     C.byref(rb.res))
+    rc = fn(sub.handle, None if pp is None else C.byref(pp), int(seed) & (2**64 - 1),
+            int(n_walkers), int(n_steps), float(dt), W.shape[0], _dptr(W), g.shape[0],
+            _dptr(g), b.size, _dptr(b), int(precision), _stream_handle(stream), C.byref(rb.res))
     _check(rc)
     out = rb.to_dict()
     if wd is not None:
@@ -448,7 +466,8 @@ def rms_server_destroy(srv) -> None:
 
 
 __all__ = ["rms_abi_version", "rms_last_error", "rms_set_option", "rms_create_substrate", "rms_destroy_substrate",
-           "rms_run", "rms_run_record", "rms_spherical_mean", "rms_cumulant_fit",
+           "rms_run", "rms_run_noalloc", "rms_run_record", "rms_spherical_mean",
+           "rms_cumulant_fit",
            "rms_server_create", "rms_server_submit", "rms_server_poll",
            "rms_server_wait", "rms_server_stats_get", "rms_server_destroy", "Substrate", "RmsError", "RMS_FP64", "RMS_MIXED", "exported_symbols",
            "DUMP_FIELDS"]

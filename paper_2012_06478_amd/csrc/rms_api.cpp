@@ -387,71 +387,96 @@ hipError_t run_malloc(void** p, size_t bytes, hipStream_t s) {
     return hipMallocFromPoolAsync(p, bytes, pool, s);
 }
 
-int DeviceRun::create(const rms_substrate& sub, const RunSetup& r, bool resumable,
-                      hipStream_t stream) {
-    s = stream;
+// Offsets of every buffer of one run inside its single device block,
+// 256-byte aligned pieces.
+struct RunLayout {
+    size_t sigma, it2, sigma_f, it2_f, thr, thr_mt, accept, start_try, gdt, trig, wstate, kg,
+        sig_shape, partial, sums, res, dirs, state, order, seg_state, seg_ctl;
+    size_t state_b, order_b, seg_b;
+    size_t total;
+};
+
+RunLayout run_layout(const rms_substrate& sub, const RunSetup& r, bool resumable) {
     const size_t L = static_cast<size_t>(sub.n_labels);
-    // One device allocation for the whole run, carved into 256-byte aligned
-    // pieces (an allocation and a free per buffer cost about 90 us each).
+    RunLayout o{};
     size_t total = 0;
     const auto take = [&total](size_t bytes) {
         const size_t off = total;
         total += (std::max<size_t>(bytes, 1) + 255) / 256 * 256;
         return off;
     };
-    const size_t o_sigma = take(L * sizeof(double));
-    const size_t o_it2 = take(L * sizeof(double));
-    const size_t o_sigma_f = take(L * sizeof(float));
-    const size_t o_it2_f = take(L * sizeof(float));
-    const size_t o_thr = take(L * L * sizeof(uint64_t));
-    const size_t o_thr_mt = take(r.thr_mt.size() * sizeof(uint32_t));
-    const size_t o_accept = take(r.accept.size() * sizeof(uint64_t));
-    const size_t o_start_try =
-        take(r.accept.empty() ? 0 : static_cast<size_t>(r.n_walkers) * sizeof(uint32_t));
-    const size_t o_gdt = take(r.gdt.size() * sizeof(double));
-    const size_t o_trig = take(2 * kTrigSize * sizeof(double));
-    const size_t o_wstate = take(static_cast<size_t>(r.n_walkers) * r.width * sizeof(double));
-    const size_t o_kg = take(r.kg.size() * sizeof(double));
-    const size_t o_sig_shape = take(r.sig_shape.size() * sizeof(int));
-    const size_t o_partial = take(static_cast<size_t>(r.n_acc) * r.n_blocks * sizeof(double));
-    const size_t o_sums = take(static_cast<size_t>(r.n_acc) * sizeof(double));
-    const size_t o_res = take(static_cast<size_t>(r.n_res) * sizeof(double));
-    const size_t o_dirs = take(r.unit.size() * sizeof(double));
-    const size_t state_b = resumable ? static_cast<size_t>(r.n_walkers) *
-                                           walker_state_bytes(r.precision, sub.label_bytes, r.n_shapes)
-                                     : 0;
-    const size_t o_state = take(state_b);
-    const size_t order_b = order_bytes(r.n_walkers);
-    const size_t o_order = take(order_b);
-    const size_t seg_b = resumable ? 0 : seg_state_bytes(r.precision, r.n_shapes, r.n_walkers);
-    const size_t o_seg_state = take(seg_b);
-    const size_t o_seg_ctl = take(seg_b > 0 ? seg_ctl_bytes(r.n_walkers) : 0);
+    o.sigma = take(L * sizeof(double));
+    o.it2 = take(L * sizeof(double));
+    o.sigma_f = take(L * sizeof(float));
+    o.it2_f = take(L * sizeof(float));
+    o.thr = take(L * L * sizeof(uint64_t));
+    o.thr_mt = take(r.thr_mt.size() * sizeof(uint32_t));
+    o.accept = take(r.accept.size() * sizeof(uint64_t));
+    o.start_try = take(r.accept.empty() ? 0 : static_cast<size_t>(r.n_walkers) * sizeof(uint32_t));
+    o.gdt = take(r.gdt.size() * sizeof(double));
+    o.trig = take(2 * kTrigSize * sizeof(double));
+    o.wstate = take(static_cast<size_t>(r.n_walkers) * r.width * sizeof(double));
+    o.kg = take(r.kg.size() * sizeof(double));
+    o.sig_shape = take(r.sig_shape.size() * sizeof(int));
+    o.partial = take(static_cast<size_t>(r.n_acc) * r.n_blocks * sizeof(double));
+    o.sums = take(static_cast<size_t>(r.n_acc) * sizeof(double));
+    o.res = take(static_cast<size_t>(r.n_res) * sizeof(double));
+    o.dirs = take(r.unit.size() * sizeof(double));
+    o.state_b = resumable ? static_cast<size_t>(r.n_walkers) *
+                                walker_state_bytes(r.precision, sub.label_bytes, r.n_shapes)
+                          : 0;
+    o.state = take(o.state_b);
+    o.order_b = order_bytes(r.n_walkers);
+    o.order = take(o.order_b);
+    o.seg_b = resumable ? 0 : seg_state_bytes(r.precision, r.n_shapes, r.n_walkers);
+    o.seg_state = take(o.seg_b);
+    o.seg_ctl = take(o.seg_b > 0 ? seg_ctl_bytes(r.n_walkers) : 0);
+    o.total = total;
+    return o;
+}
+
+int DeviceRun::create(const rms_substrate& sub, const RunSetup& r, bool resumable,
+                      hipStream_t stream) {
+    s = stream;
+    // One device allocation for the whole run, carved into 256-byte aligned
+    // pieces (an allocation and a free per buffer cost about 90 us each).
     void* base = nullptr;
-    RMS_HIP(run_malloc(&base, total, s));
+    RMS_HIP(run_malloc(&base, run_layout(sub, r, resumable).total, s));
     ptrs.push_back(base);
+    return bind(sub, r, resumable, stream, base);
+}
+
+size_t DeviceRun::layout_bytes(const rms_substrate& sub, const RunSetup& r, bool resumable) {
+    return run_layout(sub, r, resumable).total;
+}
+
+int DeviceRun::bind(const rms_substrate& sub, const RunSetup& r, bool resumable,
+                    hipStream_t stream, void* base) {
+    s = stream;
+    const RunLayout o = run_layout(sub, r, resumable);
     uint8_t* const b = static_cast<uint8_t*>(base);
-    double* d_sigma = reinterpret_cast<double*>(b + o_sigma);
-    double* d_it2 = reinterpret_cast<double*>(b + o_it2);
-    float* d_sigma_f = reinterpret_cast<float*>(b + o_sigma_f);
-    float* d_it2_f = reinterpret_cast<float*>(b + o_it2_f);
-    uint64_t* d_thr = reinterpret_cast<uint64_t*>(b + o_thr);
-    uint32_t* d_thr_mt = r.thr_mt.empty() ? nullptr : reinterpret_cast<uint32_t*>(b + o_thr_mt);
-    uint64_t* d_accept = r.accept.empty() ? nullptr : reinterpret_cast<uint64_t*>(b + o_accept);
+    double* d_sigma = reinterpret_cast<double*>(b + o.sigma);
+    double* d_it2 = reinterpret_cast<double*>(b + o.it2);
+    float* d_sigma_f = reinterpret_cast<float*>(b + o.sigma_f);
+    float* d_it2_f = reinterpret_cast<float*>(b + o.it2_f);
+    uint64_t* d_thr = reinterpret_cast<uint64_t*>(b + o.thr);
+    uint32_t* d_thr_mt = r.thr_mt.empty() ? nullptr : reinterpret_cast<uint32_t*>(b + o.thr_mt);
+    uint64_t* d_accept = r.accept.empty() ? nullptr : reinterpret_cast<uint64_t*>(b + o.accept);
     uint32_t* d_start_try =
-        r.accept.empty() ? nullptr : reinterpret_cast<uint32_t*>(b + o_start_try);
-    double* d_gdt = reinterpret_cast<double*>(b + o_gdt);
-    double* d_trig = reinterpret_cast<double*>(b + o_trig);
-    double* d_wstate = reinterpret_cast<double*>(b + o_wstate);
-    double* d_kg = reinterpret_cast<double*>(b + o_kg);
-    int* d_sig_shape = reinterpret_cast<int*>(b + o_sig_shape);
-    double* d_partial = reinterpret_cast<double*>(b + o_partial);
-    double* d_sums = reinterpret_cast<double*>(b + o_sums);
-    double* d_res = reinterpret_cast<double*>(b + o_res);
-    double* d_dirs = reinterpret_cast<double*>(b + o_dirs);
-    void* d_state = state_b ? static_cast<void*>(b + o_state) : nullptr;
-    uint32_t* d_order = order_b ? reinterpret_cast<uint32_t*>(b + o_order) : nullptr;
-    uint8_t* d_seg_state = seg_b ? b + o_seg_state : nullptr;
-    uint32_t* d_seg_ctl = seg_b ? reinterpret_cast<uint32_t*>(b + o_seg_ctl) : nullptr;
+        r.accept.empty() ? nullptr : reinterpret_cast<uint32_t*>(b + o.start_try);
+    double* d_gdt = reinterpret_cast<double*>(b + o.gdt);
+    double* d_trig = reinterpret_cast<double*>(b + o.trig);
+    double* d_wstate = reinterpret_cast<double*>(b + o.wstate);
+    double* d_kg = reinterpret_cast<double*>(b + o.kg);
+    int* d_sig_shape = reinterpret_cast<int*>(b + o.sig_shape);
+    double* d_partial = reinterpret_cast<double*>(b + o.partial);
+    double* d_sums = reinterpret_cast<double*>(b + o.sums);
+    double* d_res = reinterpret_cast<double*>(b + o.res);
+    double* d_dirs = reinterpret_cast<double*>(b + o.dirs);
+    void* d_state = o.state_b ? static_cast<void*>(b + o.state) : nullptr;
+    uint32_t* d_order = o.order_b ? reinterpret_cast<uint32_t*>(b + o.order) : nullptr;
+    uint8_t* d_seg_state = o.seg_b ? b + o.seg_state : nullptr;
+    uint32_t* d_seg_ctl = o.seg_b ? reinterpret_cast<uint32_t*>(b + o.seg_ctl) : nullptr;
     RMS_HIP(upload(d_sigma, r.sigma, s));
     RMS_HIP(upload(d_it2, r.inv_t2, s));
     RMS_HIP(upload(d_sigma_f, r.sigma_f, s));
@@ -528,6 +553,42 @@ void DeviceRun::release() {
     for (void* p : ptrs) hipFreeAsync(p, s);
     hipStreamSynchronize(s);
     ptrs.clear();
+}
+
+int execute_run(const RunSetup& r, DeviceRun& dr, hipStream_t stream, hipEvent_t ev0,
+                hipEvent_t ev1, std::chrono::steady_clock::time_point t0, rms_result* out) {
+    RMS_HIP(launch_start_try(dr.wp, stream));
+    RMS_HIP(launch_order(dr.wp, stream));
+    RMS_HIP(hipEventRecord(ev0, stream));
+    int kind = RMS_WALK_ONE_LAUNCH;
+    RMS_HIP(launch_walk(dr.wp, r.precision, stream, &kind));
+    RMS_HIP(hipEventRecord(ev1, stream));
+    RMS_HIP(launch_reduce(dr.rp, stream));
+
+    std::vector<double> res(r.n_res);
+    RMS_HIP(hipMemcpyAsync(res.data(), dr.rp.result, r.n_res * sizeof(double),
+                           hipMemcpyDeviceToHost, stream));
+    uint32_t seg_fail = 0u;
+    if (dr.wp.seg_ctl)
+        RMS_HIP(hipMemcpyAsync(&seg_fail, dr.wp.seg_ctl + kSegErrorWord, sizeof(uint32_t),
+                               hipMemcpyDeviceToHost, stream));
+    if (out->walker_dump)
+        RMS_HIP(hipMemcpyAsync(out->walker_dump, dr.wp.wstate,
+                               static_cast<size_t>(r.n_walkers) * r.width * sizeof(double),
+                               hipMemcpyDeviceToHost, stream));
+    RMS_HIP(hipStreamSynchronize(stream));
+    if (seg_fail != 0u)
+        return fail(RMS_E_WAIT_GAVE_UP,
+                    "walk: a wave of the persistent walk gave up waiting for the previous "
+                    "segment of its walkers; every wave stopped, no result");
+    float ms = 0.0f;
+    RMS_HIP(hipEventElapsedTime(&ms, ev0, ev1));
+    fill_result(r, res.data(), out);
+    out->kernel_ms = ms;
+    out->queue_s = 0.0;
+    out->walk_kernel = kind;
+    out->wall_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    return RMS_OK;
 }
 
 void fill_result(const RunSetup& r, const double* res, rms_result* out) {
@@ -713,38 +774,7 @@ int rms_run(const rms_substrate* sub, const rms_params* params, uint64_t seed, i
     } eguard{&ev0, &ev1};
     RMS_HIP(hipEventCreate(&ev0));
     RMS_HIP(hipEventCreate(&ev1));
-    RMS_HIP(rms::launch_start_try(dr.wp, stream));
-    RMS_HIP(rms::launch_order(dr.wp, stream));
-    RMS_HIP(hipEventRecord(ev0, stream));
-    int kind = RMS_WALK_ONE_LAUNCH;
-    RMS_HIP(rms::launch_walk(dr.wp, precision, stream, &kind));
-    RMS_HIP(hipEventRecord(ev1, stream));
-    RMS_HIP(rms::launch_reduce(dr.rp, stream));
-
-    std::vector<double> res(r.n_res);
-    RMS_HIP(hipMemcpyAsync(res.data(), dr.rp.result, r.n_res * sizeof(double),
-                           hipMemcpyDeviceToHost, stream));
-    std::vector<uint32_t> seg_fail(1, 0u);
-    if (dr.wp.seg_ctl)
-        RMS_HIP(hipMemcpyAsync(seg_fail.data(), dr.wp.seg_ctl + rms::kSegErrorWord,
-                               sizeof(uint32_t), hipMemcpyDeviceToHost, stream));
-    if (out->walker_dump)
-        RMS_HIP(hipMemcpyAsync(out->walker_dump, dr.wp.wstate,
-                               static_cast<size_t>(n_walkers) * r.width * sizeof(double),
-                               hipMemcpyDeviceToHost, stream));
-    RMS_HIP(hipStreamSynchronize(stream));
-    if (seg_fail[0] != 0u)
-        return rms::fail(RMS_E_WAIT_GAVE_UP,
-                         "walk: a wave of the persistent walk gave up waiting for the previous "
-                         "segment of its walkers; every wave stopped, no result");
-    float ms = 0.0f;
-    RMS_HIP(hipEventElapsedTime(&ms, ev0, ev1));
-    rms::fill_result(r, res.data(), out);
-    out->kernel_ms = ms;
-    out->queue_s = 0.0;
-    out->walk_kernel = kind;
-    out->wall_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-    return RMS_OK;
+    return rms::execute_run(r, dr, stream, ev0, ev1, t0, out);
 }
 
 int rms_set_option(int option, int64_t value) {

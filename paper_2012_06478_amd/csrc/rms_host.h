@@ -5,6 +5,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <chrono>
 #include <cmath>
 #include <cstdint>
 #include <string>
@@ -91,10 +92,24 @@ struct DeviceRun {
     std::vector<void*> ptrs;
     WalkPlan wp{};
     ReducePlan rp{};
+    // allocates the run's block from the library's pool, then bind()s it
     int create(const rms_substrate& sub, const RunSetup& r, bool resumable, hipStream_t s);
+    // device bytes of the run's block (every buffer, 256-byte aligned)
+    static size_t layout_bytes(const rms_substrate& sub, const RunSetup& r, bool resumable);
+    // lays the run's buffers out in `base` (at least layout_bytes(), owned by
+    // the caller: release() does not free it) and uploads the tables on s
+    int bind(const rms_substrate& sub, const RunSetup& r, bool resumable, hipStream_t s,
+             void* base);
     void release();
     ~DeviceRun() { release(); }
 };
+
+// The device work of rms_run on buffers already laid out by dr (start
+// attempts, walker order, walk, reductions), the copies of the results and
+// the wait for them on `stream`; ev0 and ev1 bracket the walk launch.
+// Fills `out` (wall_s from t0).
+int execute_run(const RunSetup& r, DeviceRun& dr, hipStream_t stream, hipEvent_t ev0,
+                hipEvent_t ev1, std::chrono::steady_clock::time_point t0, rms_result* out);
 
 // Copies the reduced results (device layout of ReducePlan::result) into the
 // caller's rms_result.
