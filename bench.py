@@ -226,14 +226,19 @@ def serve(args):
 
     srv = rms.rms_server_create(0, 0)
     try:
-        # capacity: a closed batch of the first 16 requests
+        # capacity: the whole trace as one closed batch (every request queued
+        # at once), so the device works on a full queue but for the drain at the end
+        c0 = rms.rms_server_stats_get(srv)
         t0 = time.perf_counter()
-        tk = [submit(srv, q) for q in reqs[:16]]
+        tk = [submit(srv, q) for q in reqs]
         for t, sh in tk:
             rms.rms_server_wait(srv, t, sh)
         cap_el = time.perf_counter() - t0
-        cap = sum(q["n_walkers"] * q["n_steps"] for q in reqs[:16]) / cap_el
-        log(f"[serve] capacity {cap:.3e} walker-steps/s (16 requests in {cap_el:.2f} s)")
+        c1 = rms.rms_server_stats_get(srv)
+        cap = sum(q["n_walkers"] * q["n_steps"] for q in reqs) / cap_el
+        cap_busy = (c1["busy_s"] - c0["busy_s"]) / cap_el
+        log(f"[serve] capacity {cap:.3e} walker-steps/s ({len(reqs)} requests queued at once, "
+            f"{cap_el:.2f} s, device busy {cap_busy:.3f})")
         work = np.array([q["n_walkers"] * q["n_steps"] for q in reqs], float)
         rate = args.serve_load * cap / work.mean()  # requests per second
         rng = np.random.default_rng(11)
@@ -281,7 +286,8 @@ def serve(args):
         "p99_latency_s": float(np.percentile(lat, 99)),
         "p50_queue_s": float(np.percentile(queue, 50)),
         "p99_queue_s": float(np.percentile(queue, 99)),
-        "capacity_walker_steps_per_s": cap, "offered_load": args.serve_load,
+        "capacity_walker_steps_per_s": cap, "capacity_device_busy_frac": cap_busy,
+        "offered_load": args.serve_load,
         "device_busy_frac": (st["busy_s"] - st0["busy_s"]) / (end - start),
         "launches": st["launches"] - st0["launches"],
         "max_signal_err_vs_fp64": err,

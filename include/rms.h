@@ -344,9 +344,11 @@ int rms_cumulant_fit(int n_b, const double* bvals, int n_dirs, const double* sig
  * arrival order while their device memory fits in the budget, and advances
  * every admitted request by a slice of steps in one packed launch per slice
  * (requests of different sizes share a launch, grouped by precision, label
- * width and shape count).  A request that arrives while others run joins at
- * the next slice boundary; a finished request's results are reduced at once
- * and its memory freed for the next admission.  Walker trajectories depend only
+ * width and shape count).  The next slice is queued on the device before the
+ * server waits for the current one, so the device does not idle between
+ * slices.  A request that arrives while others run joins at the next slice
+ * built; a finished request's results are reduced and copied in the slice
+ * that finishes it, and its memory is freed for the next admission.  Walker trajectories depend only
  * on (seed, walker, step) and each request is reduced on its own in a fixed
  * order, so a request's results are bit-identical alone, in any mix and to
  * rms_run with the same arguments.

@@ -1,22 +1,26 @@
 // Serving runtime: continuous batching of simulation requests on one GPU.
 //
 // Scheduling is per slice of steps (iteration-level batching).  One host
-// thread owns the device work:
-//   1. admit pending requests in arrival order while their device memory fits
-//      the budget (buffers allocated and inputs uploaded on the server's
-//      stream);
-//   2. build one work list per group of admitted requests that share
-//      precision, label width, shape count and whether membranes absorb: a
-//      block per 256 walkers of each
-//      request, each advancing its walkers from the request's current step by
-//      the slice length (or to the end);
-//   3. run the packed walk launches (walker states stay in HBM between
-//      slices), time them with HIP events;
-//   4. reduce every request that reached its last step (fixed-order fp64
-//      kernels on its own buffers), copy its results to the host, free its
-//      memory and wake its waiters.
-// Requests submitted during a slice are admitted before the next one, so
-// their walkers share launches with requests already running.
+// thread owns the device work and keeps the device fed: it enqueues slice
+// k + 1 before it waits for slice k, so the stream always holds the next
+// launch while the host handles the previous one.  Per iteration it
+//   1. admits pending requests in arrival order while their device memory
+//      fits the budget (buffers allocated from the library's stream-ordered
+//      pool and inputs uploaded on the server's stream, walker order built);
+//   2. if fewer than kDepth slices are in flight, enqueues the next slice:
+//      one packed launch per group of admitted requests that share
+//      precision, label width, shape count and whether membranes absorb,
+//      with a block per 256 walkers of each request advancing them from the
+//      request's scheduled step by the slice length (or to the end; requests
+//      that end early come last in their launch), then, for every request
+//      whose last steps the slice holds, its fixed-order fp64 reduction, the
+//      copy of its results to a pinned host block and the stream-ordered
+//      release of its device memory;
+//   3. otherwise waits for the oldest slice in flight and completes the
+//      requests it finished (their results are already in host memory).
+// Requests submitted while slices run are admitted before the next slice is
+// built, so their walkers share launches with requests already running, and
+// the memory that finished requests free is admitted again in stream order.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -41,12 +45,19 @@ double seconds_since(clock_type::time_point t0, clock_type::time_point t) {
     return std::chrono::duration<double>(t - t0).count();
 }
 
+// Slices in flight at once: the one running and the one queued behind it.
+constexpr int kDepth = 2;
+// Largest result record of a request: kAccFixed + 2 n_sig + 2 n_dirs doubles.
+constexpr size_t kResMax = rms::kAccFixed + 2 * RMS_MAX_SIGNALS + 2 * RMS_MAX_SIGNALS;
+
 struct Request {
     rms_ticket id = 0;
     rms::RunSetup setup;  // holds copies of every input array
     rms::DeviceRun dev;
     size_t bytes = 0;
-    int64_t steps_done = 0;
+    int64_t steps_sched = 0;   // steps enqueued on the device
+    bool last_sched = false;   // the slice with its last steps is enqueued
+    double* h_res = nullptr;   // pinned block its results are copied to
     enum State { kPending, kActive, kDone, kFailed } state = kPending;
     int rc = RMS_OK;
     std::string err;
@@ -54,12 +65,31 @@ struct Request {
     clock_type::time_point t_submit, t_admit, t_done;
 };
 
+// Device work list of one slice: items and plans, grown as needed
+// (stream-ordered, so a buffer is replaced only behind the work that read it).
+struct WorkBuffer {
+    rms::PackedItem* items = nullptr;
+    size_t items_cap = 0;
+    rms::WalkPlan* plans = nullptr;
+    size_t plans_cap = 0;
+};
+
+struct Slice {
+    hipEvent_t ev_begin = nullptr, ev_end = nullptr;
+    std::vector<Request*> members;    // every request with steps in the slice
+    std::vector<Request*> finishing;  // those whose last steps it holds
+    std::vector<rms::PackedItem> items;  // host copies, alive until the slice is done
+    std::vector<rms::WalkPlan> plans;
+    hipError_t err = hipSuccess;
+    std::string what;
+};
+
 }  // namespace
 
 struct rms_server {
     int device = 0;
     hipStream_t stream = nullptr;
-    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    hipEvent_t events[2 * kDepth] = {};
     size_t budget = 0, in_use = 0;
     int slice_steps = 0;
     std::mutex m;
@@ -73,14 +103,16 @@ struct rms_server {
     // statistics
     int64_t submitted = 0, completed = 0, failed = 0, launches = 0, walker_steps = 0;
     double busy_s = 0.0;
-    // device work-list buffers, grown as needed (worker thread only)
-    rms::PackedItem* d_items = nullptr;
-    size_t items_cap = 0;
-    rms::WalkPlan* d_plans = nullptr;
-    size_t plans_cap = 0;
+    // worker thread only
+    WorkBuffer bufs[kDepth];
+    int next_buf = 0;
+    std::vector<double*> pinned_free, pinned_all;
 
     void loop();
+    void enqueue_slice(std::deque<Slice>& inflight);
+    void complete_slice(Slice& sl);
     void finish(Request* r, int rc, const std::string& err);
+    void free_device(Request* r);
 };
 
 namespace {
@@ -89,21 +121,34 @@ template <typename T>
 hipError_t grow(T** p, size_t* cap, size_t need, hipStream_t s) {
     if (need <= *cap) return hipSuccess;
     if (*p) {
-        hipStreamSynchronize(s);
-        hipFree(*p);
+        hipFreeAsync(*p, s);
         *p = nullptr;
     }
-    size_t n = std::max<size_t>(need, 2 * *cap);
-    hipError_t e = hipMalloc(reinterpret_cast<void**>(p), n * sizeof(T));
+    const size_t n = std::max<size_t>(need, 2 * *cap);
+    void* q = nullptr;
+    hipError_t e = rms::run_malloc(&q, n * sizeof(T), s);
+    *p = static_cast<T*>(q);
     *cap = e == hipSuccess ? n : 0;
     return e;
 }
 
 }  // namespace
 
-// Called by the worker with the lock NOT held.
+// Stream-ordered release of a request's device memory (behind every launch
+// already enqueued that reads it).
+void rms_server::free_device(Request* r) {
+    for (void* p : r->dev.ptrs) hipFreeAsync(p, stream);
+    r->dev.ptrs.clear();
+}
+
+// Worker thread; the lock is NOT held.
 void rms_server::finish(Request* r, int rc, const std::string& err) {
-    r->dev.release();
+    free_device(r);
+    if (r->h_res) {
+        if (rc == RMS_OK) r->res.assign(r->h_res, r->h_res + r->setup.n_res);
+        if (static_cast<size_t>(r->setup.n_res) <= kResMax) pinned_free.push_back(r->h_res);
+        r->h_res = nullptr;
+    }
     std::lock_guard<std::mutex> lk(m);
     in_use -= r->bytes;
     r->rc = rc;
@@ -119,13 +164,129 @@ void rms_server::finish(Request* r, int rc, const std::string& err) {
     cv_done.notify_all();
 }
 
+void rms_server::enqueue_slice(std::deque<Slice>& inflight) {
+    inflight.emplace_back();
+    Slice& sl = inflight.back();
+    sl.ev_begin = events[2 * next_buf];
+    sl.ev_end = events[2 * next_buf + 1];
+    WorkBuffer& wb = bufs[next_buf];
+    next_buf = (next_buf + 1) % kDepth;
+
+    // slice length
+    int64_t walkers = 0;
+    for (Request* r : active)
+        if (!r->last_sched) walkers += r->setup.n_walkers;
+    int64_t S = slice_steps;
+    if (S <= 0) S = std::max<int64_t>(64, std::min<int64_t>(1 << 20, 4000000000LL / walkers));
+    S = (S + 3) / 4 * 4;  // slices start on a multiple of 4 steps (both Philox streams)
+
+    // one packed launch per (precision, label width, shape count, absorbing)
+    std::map<std::tuple<int, int, int, bool>, std::vector<Request*>> groups;
+    for (Request* r : active)
+        if (!r->last_sched)
+            groups[{r->setup.precision, r->setup.sub->dev_label_bytes, r->setup.n_shapes,
+                    !r->setup.thr_mt.empty()}]
+                .push_back(r);
+    std::vector<std::tuple<int, int, int, bool, size_t, size_t>> todo;  // key, item range
+    for (auto& g : groups) {
+        // requests that run the whole slice first, those that end early last
+        std::stable_sort(g.second.begin(), g.second.end(), [S](Request* a, Request* b) {
+            return std::min(S, a->setup.n_steps - a->steps_sched) >
+                   std::min(S, b->setup.n_steps - b->steps_sched);
+        });
+        const size_t first = sl.items.size();
+        for (Request* r : g.second) {
+            const int plan = static_cast<int>(sl.plans.size());
+            sl.plans.push_back(r->dev.wp);
+            const int64_t b = r->steps_sched;
+            const int64_t e = std::min(r->setup.n_steps, b + S);
+            // slot block k of an ordered run belongs on XCD k mod 8: start the
+            // run at a launch block index that is a multiple of 8 (the filler
+            // items' slots lie past the run's slots, so their threads exit)
+            const int64_t n_slots = r->dev.wp.n_slots;
+            if (r->dev.wp.order)
+                while ((sl.items.size() - first) % 8 != 0)
+                    sl.items.push_back(rms::PackedItem{n_slots, plan, static_cast<uint32_t>(b),
+                                                       static_cast<uint32_t>(e), 0u});
+            for (int64_t w = 0; w < n_slots; w += rms::kBlock)
+                sl.items.push_back(rms::PackedItem{w, plan, static_cast<uint32_t>(b),
+                                                   static_cast<uint32_t>(e), 0u});
+            r->steps_sched = e;
+            sl.members.push_back(r);
+            if (e == r->setup.n_steps) {
+                r->last_sched = true;
+                sl.finishing.push_back(r);
+            }
+        }
+        todo.emplace_back(std::get<0>(g.first), std::get<1>(g.first), std::get<2>(g.first),
+                          std::get<3>(g.first), first, sl.items.size() - first);
+    }
+    hipError_t e = grow(&wb.items, &wb.items_cap, sl.items.size(), stream);
+    if (e == hipSuccess) e = grow(&wb.plans, &wb.plans_cap, sl.plans.size(), stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(wb.items, sl.items.data(), sl.items.size() * sizeof(rms::PackedItem),
+                           hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(wb.plans, sl.plans.data(), sl.plans.size() * sizeof(rms::WalkPlan),
+                           hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) e = hipEventRecord(sl.ev_begin, stream);
+    for (auto& L : todo) {
+        if (e != hipSuccess) break;
+        e = rms::launch_walk_packed(wb.items + std::get<4>(L), static_cast<int>(std::get<5>(L)),
+                                    wb.plans, std::get<0>(L), std::get<1>(L), std::get<2>(L),
+                                    std::get<3>(L), stream);
+    }
+    if (e != hipSuccess) sl.what = "packed walk";
+    for (Request* r : sl.finishing) {
+        if (e != hipSuccess) break;
+        e = rms::launch_reduce(r->dev.rp, stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(r->h_res, r->dev.rp.result, r->setup.n_res * sizeof(double),
+                               hipMemcpyDeviceToHost, stream);
+        if (e == hipSuccess) free_device(r);
+        else sl.what = "reduction";
+    }
+    if (e == hipSuccess) e = hipEventRecord(sl.ev_end, stream);
+    sl.err = e;
+    {
+        std::lock_guard<std::mutex> lk(m);
+        launches += static_cast<int64_t>(todo.size());
+    }
+}
+
+void rms_server::complete_slice(Slice& sl) {
+    hipError_t e = sl.err;
+    if (e == hipSuccess) e = hipEventSynchronize(sl.ev_end);
+    float ms = 0.0f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, sl.ev_begin, sl.ev_end);
+    if (e != hipSuccess) {
+        // the device work of every admitted request is in doubt
+        const std::string msg = std::string(sl.what.empty() ? "slice" : sl.what) + ": " +
+                                hipGetErrorString(e);
+        std::vector<Request*> all_active;
+        all_active.swap(active);
+        for (Request* r : all_active) finish(r, RMS_E_DEVICE, msg);
+        return;
+    }
+    {
+        std::lock_guard<std::mutex> lk(m);
+        busy_s += ms * 1e-3;
+    }
+    for (Request* r : sl.finishing) {
+        active.erase(std::find(active.begin(), active.end(), r));
+        finish(r, RMS_OK, "");
+    }
+}
+
 void rms_server::loop() {
     hipSetDevice(device);
+    std::deque<Slice> inflight;
     std::vector<Request*> admit;
     for (;;) {
         {
             std::unique_lock<std::mutex> lk(m);
-            cv_work.wait(lk, [&] { return stop || !pending.empty() || !active.empty(); });
+            if (inflight.empty() && active.empty())
+                cv_work.wait(lk, [&] { return stop || !pending.empty(); });
             if (stop) break;
             while (!pending.empty() && in_use + pending.front()->bytes <= budget) {
                 Request* r = pending.front();
@@ -135,6 +296,22 @@ void rms_server::loop() {
             }
         }
         for (Request* r : admit) {
+            const bool big = static_cast<size_t>(r->setup.n_res) > kResMax;  // many directions
+            if (big || pinned_free.empty()) {
+                void* h = nullptr;
+                const size_t n = big ? static_cast<size_t>(r->setup.n_res) : kResMax;
+                if (hipHostMalloc(&h, n * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+                    finish(r, RMS_E_OOM, "pinned result buffer");
+                    continue;
+                }
+                pinned_all.push_back(static_cast<double*>(h));
+                if (!big) pinned_free.push_back(static_cast<double*>(h));
+                else r->h_res = static_cast<double*>(h);
+            }
+            if (!big) {
+                r->h_res = pinned_free.back();
+                pinned_free.pop_back();
+            }
             int rc = r->dev.create(*r->setup.sub, r->setup, true, stream);
             if (rc == RMS_OK) {
                 hipError_t eo = rms::launch_start_try(r->dev.wp, stream);
@@ -151,100 +328,21 @@ void rms_server::loop() {
             active.push_back(r);
         }
         admit.clear();
-        if (active.empty()) continue;  // active is only touched by this thread
-
-        // slice length
-        int64_t walkers = 0;
-        for (Request* r : active) walkers += r->setup.n_walkers;
-        int64_t S = slice_steps;
-        if (S <= 0) S = std::max<int64_t>(64, std::min<int64_t>(1 << 20, 4000000000LL / walkers));
-        S = (S + 3) / 4 * 4;  // slices start on a multiple of 4 steps (both Philox streams)
-
-        // one packed launch per (precision, label width, shape count, absorbing)
-        std::map<std::tuple<int, int, int, bool>, std::vector<Request*>> groups;
-        for (Request* r : active)
-            groups[{r->setup.precision, r->setup.sub->dev_label_bytes, r->setup.n_shapes,
-                    !r->setup.thr_mt.empty()}]
-                .push_back(r);
-        std::vector<rms::WalkPlan> plans;
-        std::vector<rms::PackedItem> items;
-        // key, item range
-        std::vector<std::tuple<int, int, int, bool, size_t, size_t>> launches_todo;
-        std::vector<int64_t> step_end(active.size());
-        std::map<Request*, size_t> index;
-        for (size_t i = 0; i < active.size(); ++i) index[active[i]] = i;
-        for (auto& g : groups) {
-            const size_t first = items.size();
-            for (Request* r : g.second) {
-                const int plan = static_cast<int>(plans.size());
-                plans.push_back(r->dev.wp);
-                const int64_t b = r->steps_done;
-                const int64_t e = std::min(r->setup.n_steps, b + S);
-                step_end[index[r]] = e;
-                // slot block k of an ordered run belongs on XCD k mod 8: start the
-                // run at a launch block index that is a multiple of 8 (the filler
-                // items' slots lie past the run's slots, so their threads exit)
-                const int64_t n_slots = r->dev.wp.n_slots;
-                if (r->dev.wp.order)
-                    while ((items.size() - first) % 8 != 0)
-                        items.push_back(rms::PackedItem{n_slots, plan, static_cast<uint32_t>(b),
-                                                        static_cast<uint32_t>(e), 0u});
-                for (int64_t w = 0; w < n_slots; w += rms::kBlock)
-                    items.push_back(rms::PackedItem{w, plan, static_cast<uint32_t>(b),
-                                                    static_cast<uint32_t>(e), 0u});
-            }
-            launches_todo.emplace_back(std::get<0>(g.first), std::get<1>(g.first),
-                                       std::get<2>(g.first), std::get<3>(g.first), first,
-                                       items.size() - first);
+        const bool work = std::any_of(active.begin(), active.end(),
+                                      [](Request* r) { return !r->last_sched; });
+        if (work && inflight.size() < static_cast<size_t>(kDepth)) {
+            enqueue_slice(inflight);
+            continue;
         }
-        hipError_t e = grow(&d_items, &items_cap, items.size(), stream);
-        if (e == hipSuccess) e = grow(&d_plans, &plans_cap, plans.size(), stream);
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(d_items, items.data(), items.size() * sizeof(rms::PackedItem),
-                               hipMemcpyHostToDevice, stream);
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(d_plans, plans.data(), plans.size() * sizeof(rms::WalkPlan),
-                               hipMemcpyHostToDevice, stream);
-        if (e == hipSuccess) e = hipEventRecord(ev0, stream);
-        for (auto& L : launches_todo) {
-            if (e != hipSuccess) break;
-            e = rms::launch_walk_packed(d_items + std::get<4>(L), static_cast<int>(std::get<5>(L)),
-                                        d_plans, std::get<0>(L), std::get<1>(L), std::get<2>(L),
-                                        std::get<3>(L), stream);
-        }
-        if (e == hipSuccess) e = hipEventRecord(ev1, stream);
-        if (e == hipSuccess) e = hipStreamSynchronize(stream);
-        float ms = 0.0f;
-        if (e == hipSuccess) hipEventElapsedTime(&ms, ev0, ev1);
-        {
-            std::lock_guard<std::mutex> lk(m);
-            ++launches;
-            busy_s += ms * 1e-3;
-        }
-        std::vector<Request*> still;
-        for (size_t i = 0; i < active.size(); ++i) {
-            Request* r = active[i];
-            if (e != hipSuccess) {
-                finish(r, RMS_E_DEVICE, std::string("packed walk: ") + hipGetErrorString(e));
-                continue;
-            }
-            r->steps_done = step_end[i];
-            if (r->steps_done < r->setup.n_steps) {
-                still.push_back(r);
-                continue;
-            }
-            r->res.assign(r->setup.n_res, 0.0);
-            hipError_t er = rms::launch_reduce(r->dev.rp, stream);
-            if (er == hipSuccess)
-                er = hipMemcpyAsync(r->res.data(), r->dev.rp.result, r->res.size() * sizeof(double),
-                                    hipMemcpyDeviceToHost, stream);
-            if (er == hipSuccess) er = hipStreamSynchronize(stream);
-            finish(r, er == hipSuccess ? RMS_OK : RMS_E_DEVICE,
-                   er == hipSuccess ? "" : std::string("reduction: ") + hipGetErrorString(er));
-        }
-        active.swap(still);
+        if (inflight.empty()) continue;
+        complete_slice(inflight.front());
+        inflight.pop_front();
     }
-    // stopping: fail whatever is left
+    // stopping: let the slices in flight end, then fail whatever is left
+    while (!inflight.empty()) {
+        complete_slice(inflight.front());
+        inflight.pop_front();
+    }
     std::vector<Request*> left;
     {
         std::lock_guard<std::mutex> lk(m);
@@ -268,14 +366,14 @@ int rms_server_create(size_t mem_budget_bytes, int slice_steps, rms_server** out
     if (!s) return rms::fail(RMS_E_OOM, "host allocation failed");
     hipError_t e = hipGetDevice(&s->device);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking);
-    if (e == hipSuccess) e = hipEventCreate(&s->ev0);
-    if (e == hipSuccess) e = hipEventCreate(&s->ev1);
+    for (hipEvent_t& ev : s->events)
+        if (e == hipSuccess) e = hipEventCreate(&ev);
     size_t free_b = 0, total_b = 0;
     if (e == hipSuccess) e = hipMemGetInfo(&free_b, &total_b);
     if (e != hipSuccess) {
         const int rc = rms::hip_fail("server setup", e);
-        if (s->ev1) hipEventDestroy(s->ev1);
-        if (s->ev0) hipEventDestroy(s->ev0);
+        for (hipEvent_t ev : s->events)
+            if (ev) hipEventDestroy(ev);
         if (s->stream) hipStreamDestroy(s->stream);
         delete s;
         return rc;
@@ -378,11 +476,13 @@ void rms_server_destroy(rms_server* srv) {
     }
     if (srv->worker.joinable()) srv->worker.join();
     hipSetDevice(srv->device);
+    for (WorkBuffer& wb : srv->bufs) {
+        if (wb.items) hipFreeAsync(wb.items, srv->stream);
+        if (wb.plans) hipFreeAsync(wb.plans, srv->stream);
+    }
     hipStreamSynchronize(srv->stream);
-    if (srv->d_items) hipFree(srv->d_items);
-    if (srv->d_plans) hipFree(srv->d_plans);
-    hipEventDestroy(srv->ev0);
-    hipEventDestroy(srv->ev1);
+    for (double* h : srv->pinned_all) hipHostFree(h);
+    for (hipEvent_t ev : srv->events) hipEventDestroy(ev);
     hipStreamDestroy(srv->stream);
     delete srv;
 }
