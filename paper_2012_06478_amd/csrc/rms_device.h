@@ -41,9 +41,10 @@
 // 2.1.1).  Directions take u1, u2 from the top 24 bits of the same words and
 // use the hardware sine and cosine (argument in revolutions, so 2 pi u needs
 // no range reduction); face tests, end points and budgets are fp32; the
-// displacement is the exact count of voxels crossed plus the fp32 offset
-// change; the phase and R accumulate in fp64 (a double FMA issues at the fp32
-// rate on gfx950, so this costs less than a compensated fp32 sum).
+// displacement is a double holding the whole voxels crossed minus the start
+// offset (exact) plus the fp32 offset; the phase and R accumulate in fp64 (a
+// double FMA issues at the fp32 rate on gfx950, so this costs less than a
+// compensated fp32 sum).
 // Permeation uses the same 32-bit thresholds and words as the fp64 form.
 #pragma once
 
@@ -562,9 +563,9 @@ struct WalkerMixedT {
     uint32_t lb;  // byte offset of the voxel's entry in the padded volume
     int l, l0;
     uint32_t nface, nhit, nperm;
-    int n[3];     // voxels crossed per axis (signed), exact
-    float o[3];   // offset in the voxel, [0, 1]
-    float o0[3];  // offset at the start
+    float o[3];      // offset in the voxel, [0, 1]
+    double base[3];  // n - o0, n the signed count of voxels crossed and o0 the
+                     // start offset (exact in double): the displacement is base + o
     float sig, it2;
     double R;             // sum of t_c / T2_c
     double ph[kShapes][3];  // phase vector, voxel units x ms
@@ -573,10 +574,11 @@ struct WalkerMixedT {
                                          const Ids& id) {
         const Start s = draw_start(p, id);
         lb = static_cast<uint32_t>(padded_index(p, s.lin)) * sizeof(LabelT);
-        o[0] = o0[0] = unit_open_f(s.wox);
-        o[1] = o0[1] = unit_open_f(s.woy);
-        o[2] = o0[2] = unit_open_f(s.woz);
-        n[0] = n[1] = n[2] = 0;
+        o[0] = unit_open_f(s.wox);
+        o[1] = unit_open_f(s.woy);
+        o[2] = unit_open_f(s.woz);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) base[a] = -static_cast<double>(o[a]);
         l = l0 = entry(lab, lb);  // interior: no flags
         sig = p.sigma_f[l];
         it2 = p.inv_t2_f[l];
@@ -716,27 +718,26 @@ struct WalkerMixedT {
             const float t = (refl >> a) & 1u ? (pos ? 2.0f : 0.0f) - fr : fr;
             const float shift = ps ? (pos ? 1.0f : -1.0f) : 0.0f;
             o[a] = fminf(fmaxf(t - shift, 0.0f), 1.0f);
-            n[a] += ps ? (pos ? 1 : -1) : 0;
+            base[a] += static_cast<double>(shift);  // exact: whole voxels
         }
+        // displacement base + o = n + o - o0 (one rounding at most, far below
+        // the fp32 offset's own resolution); a zero gradient sample adds
+        // exactly nothing, so no test for it
+        double dsp[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) dsp[a] = base[a] + static_cast<double>(o[a]);
 #pragma unroll
         for (int q = 0; q < NS; ++q) {
             const double g = p.gdt[static_cast<int64_t>(q) * p.n_steps + i0];
-            if (g != 0.0) {
 #pragma unroll
-                for (int a = 0; a < 3; ++a)  // displacement n + o - o0, exact in double
-                    ph[q][a] = fma(g, static_cast<double>(n[a]) + (static_cast<double>(o[a]) -
-                                                                   static_cast<double>(o0[a])),
-                                   ph[q][a]);
-            }
+            for (int a = 0; a < 3; ++a) ph[q][a] = fma(g, dsp[a], ph[q][a]);
         }
     }
 
     __device__ __forceinline__ void finish(const WalkPlan& p, double* out) const {
         const Coords k = volume_coords(p, static_cast<int>(lb / sizeof(LabelT)));
 #pragma unroll
-        for (int a = 0; a < 3; ++a)
-            out[a] = (static_cast<double>(n[a]) +
-                      (static_cast<double>(o[a]) - static_cast<double>(o0[a]))) * p.voxel_um;
+        for (int a = 0; a < 3; ++a) out[a] = (base[a] + static_cast<double>(o[a])) * p.voxel_um;
         out[3] = R;
         out[4] = l;
         out[5] = k.c[0];
