@@ -371,7 +371,7 @@ hipError_t run_pool(hipMemPool_t* out) {
         uint64_t keep = kPoolKeepBytes;
         e = hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
         if (e != hipSuccess) {
-            hipMemPoolDestroy(pool);
+            (void)hipMemPoolDestroy(pool);
             return e;
         }
         pools[dev] = pool;
@@ -549,9 +549,9 @@ int DeviceRun::bind(const rms_substrate& sub, const RunSetup& r, bool resumable,
 
 void DeviceRun::release() {
     if (ptrs.empty()) return;
-    hipStreamSynchronize(s);
-    for (void* p : ptrs) hipFreeAsync(p, s);
-    hipStreamSynchronize(s);
+    (void)hipStreamSynchronize(s);
+    for (void* p : ptrs) (void)hipFreeAsync(p, s);
+    (void)hipStreamSynchronize(s);
     ptrs.clear();
 }
 
@@ -730,11 +730,11 @@ int rms_create_substrate(const void* labels, int label_bytes, const int64_t dims
 void rms_destroy_substrate(rms_substrate* sub) {
     if (!sub) return;
     int prev = 0;
-    hipGetDevice(&prev);
-    hipSetDevice(sub->device);
-    if (sub->d_labels) hipFree(sub->d_labels);
-    if (sub->d_allowed) hipFree(sub->d_allowed);
-    hipSetDevice(prev);
+    (void)hipGetDevice(&prev);
+    (void)hipSetDevice(sub->device);
+    if (sub->d_labels) (void)hipFree(sub->d_labels);
+    if (sub->d_allowed) (void)hipFree(sub->d_allowed);
+    (void)hipSetDevice(prev);
     delete sub;
 }
 
@@ -754,7 +754,7 @@ int rms_run(const rms_substrate* sub, const rms_params* params, uint64_t seed, i
     RMS_HIP(hipGetDevice(&prev_dev));
     struct DeviceGuard {
         int prev;
-        ~DeviceGuard() { hipSetDevice(prev); }
+        ~DeviceGuard() { (void)hipSetDevice(prev); }
     } guard{prev_dev};
     RMS_HIP(hipSetDevice(sub->device));
 
@@ -768,8 +768,8 @@ int rms_run(const rms_substrate* sub, const rms_params* params, uint64_t seed, i
         hipEvent_t* a;
         hipEvent_t* b;
         ~EventGuard() {
-            if (*a) hipEventDestroy(*a);
-            if (*b) hipEventDestroy(*b);
+            if (*a) (void)hipEventDestroy(*a);
+            if (*b) (void)hipEventDestroy(*b);
         }
     } eguard{&ev0, &ev1};
     RMS_HIP(hipEventCreate(&ev0));
@@ -876,7 +876,7 @@ int rms_run_record(const rms_substrate* sub, const rms_params* params, uint64_t 
     RMS_HIP(hipGetDevice(&prev_dev));
     struct DeviceGuard {
         int prev;
-        ~DeviceGuard() { hipSetDevice(prev); }
+        ~DeviceGuard() { (void)hipSetDevice(prev); }
     } guard{prev_dev};
     RMS_HIP(hipSetDevice(sub->device));
 
@@ -944,13 +944,13 @@ int rms_run_record(const rms_substrate* sub, const rms_params* params, uint64_t 
             if (*b) {
                 hipEvent_t e = nullptr;
                 if (hipEventCreateWithFlags(&e, hipEventDisableTiming) == hipSuccess) {
-                    hipEventRecord(e, *b);
-                    hipStreamWaitEvent(a, e, 0);
-                    hipEventDestroy(e);
+                    (void)hipEventRecord(e, *b);
+                    (void)hipStreamWaitEvent(a, e, 0);
+                    (void)hipEventDestroy(e);
                 }
-                hipStreamDestroy(*b);
+                (void)hipStreamDestroy(*b);
             }
-            for (hipEvent_t e : *ev) hipEventDestroy(e);
+            for (hipEvent_t e : *ev) (void)hipEventDestroy(e);
         }
     } sguard{stream, &sb, &events};
     const auto new_event = [&](bool timing, hipEvent_t* e) -> hipError_t {

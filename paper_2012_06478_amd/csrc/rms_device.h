@@ -348,7 +348,7 @@ struct WalkerF64T {
     int l, l0;       // label, label at the start
     uint32_t nface, nhit, nperm;
     double o[3];
-    double sig, it2;
+    double sig, dti2;  // step length (voxel units) and dt / T2 of the current label
     double d[3];  // displacement, voxel units
     double R;
     double ph[kShapes][3];  // phase vector, voxel units x ms
@@ -362,7 +362,7 @@ struct WalkerF64T {
         o[2] = unit_open(s.woz);
         l = l0 = entry(lab, lb);  // interior: no flags
         sig = p.sigma[l];
-        it2 = p.inv_t2[l];
+        dti2 = p.dt * p.inv_t2[l];
         d[0] = d[1] = d[2] = 0.0;
         R = 0.0;
 #pragma unroll
@@ -400,20 +400,21 @@ struct WalkerF64T {
         int nev = __builtin_popcount(evm);
         int ax[3];
         event_order(g, m, ax);
-        // Entries of the voxels the events reach if every face passes (the
-        // common case), loaded together so the step waits for memory once
-        // rather than once per event.
+        // Offsets and entries of the voxels the events reach if every face
+        // passes (the common case), loaded together so the step waits for
+        // memory once rather than once per event.
         const int nev0 = nev;
-        uint32_t rsp[3];  // rsp[k] is set, and read, only for k < nev0
+        uint32_t cpath[3], rsp[3];  // rsp[k] is set, and read, only for k < nev0
         {
             uint32_t c = lb;
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
                 c += static_cast<uint32_t>(pick(sst, ax[k]));
+                cpath[k] = c;
                 if (k < nev0) rsp[k] = entry(lab, c);
             }
         }
-        bool spec = true;  // no reflection yet: rsp holds the entries of the voxels reached
+        bool spec = true;  // every face so far passed: cpath and rsp hold the voxels reached
 
         // gap to axis a's face, and the path length to it (divided out only
         // after a permeation)
@@ -423,7 +424,7 @@ struct WalkerF64T {
         };
         const auto face_len = [&](int a) { return face_gap(a) / fabs(pick(v, a)); };
         double P = 0.0, tau = 1.0;
-        uint32_t passed = 0, refl = 0;
+        uint32_t done = 0, refl = 0;  // axes whose face the step reached; those it reflected at
         uint32_t rawc = 0;  // entry of the voxel last passed into (its halo flags)
         int mw_used = 0;
         uint4 mw;  // words of substream 3, computed before the second membrane hit reads them
@@ -431,11 +432,15 @@ struct WalkerF64T {
         for (int k = 0; k < 3; ++k) {
             if (k < nev) {
                 const int a = ax[k];
-                ++nface;
-                const uint32_t nbk = lb + static_cast<uint32_t>(pick(sst, a));
-                uint32_t raw;
-                if (spec && k < nev0) raw = rsp[k];
-                else raw = entry(lab, nbk);
+                done |= 1u << a;
+                uint32_t nbk, raw;
+                if (spec && k < nev0) {
+                    nbk = cpath[k];
+                    raw = rsp[k];
+                } else {  // after a reflection, or a face a permeation brought in
+                    nbk = lb + static_cast<uint32_t>(pick(sst, a));
+                    raw = entry(lab, nbk);
+                }
                 const int nl = static_cast<int>(raw & LabelBits<LabelT>::kMask);
                 bool cross = true;
                 if (nl != l) {
@@ -459,12 +464,12 @@ struct WalkerF64T {
                         ++nperm;
                         const double ek = fmax(face_len(a), P);
                         const double dtau = fmin((ek - P) / sig, tau);
-                        R = fma(p.dt * dtau, it2, R);
+                        R = fma(dtau, dti2, R);
                         tau -= dtau;
                         P = ek;
                         l = nl;
                         sig = p.sigma[nl];
-                        it2 = p.inv_t2[nl];
+                        dti2 = p.dt * p.inv_t2[nl];
                         // the later faces, in order, that lie inside the new budget:
                         // face_len < pend compared as gap < pend |v| (no division)
                         const double pend = fma(tau, sig, P);
@@ -476,7 +481,6 @@ struct WalkerF64T {
                     }
                 }
                 if (cross) {
-                    passed |= 1u << a;
                     lb = nbk;
                     rawc = raw;
                 } else {
@@ -485,11 +489,13 @@ struct WalkerF64T {
                 }
             }
         }
+        const uint32_t passed = done & ~refl;
+        nface += __builtin_popcount(done);
         const uint32_t halo = rawc >> LabelBits<LabelT>::kShift;
         if (__builtin_expect(halo != 0u, 0))
             lb = wrap_halo(p, lb, halo, posm, static_cast<int>(sizeof(LabelT)));
         const double lend = fma(tau, sig, P);
-        R = fma(p.dt * tau, it2, R);
+        R = fma(tau, dti2, R);
         // End point per axis from the free end point o + lend v: mirrored about
         // the face after a reflection; after a pass the same point, one voxel
         // further along the axis.  The displacement is that point minus o.
@@ -566,7 +572,7 @@ struct WalkerMixedT {
     float o[3];      // offset in the voxel, [0, 1]
     double base[3];  // n - o0, n the signed count of voxels crossed and o0 the
                      // start offset (exact in double): the displacement is base + o
-    float sig, it2;
+    float sig, dti2;  // step length (voxel units) and dt / T2 of the current label
     double R;             // sum of t_c / T2_c
     double ph[kShapes][3];  // phase vector, voxel units x ms
 
@@ -581,7 +587,7 @@ struct WalkerMixedT {
         for (int a = 0; a < 3; ++a) base[a] = -static_cast<double>(o[a]);
         l = l0 = entry(lab, lb);  // interior: no flags
         sig = p.sigma_f[l];
-        it2 = p.inv_t2_f[l];
+        dti2 = static_cast<float>(p.dt) * p.inv_t2_f[l];
         R = 0.0;
 #pragma unroll
         for (int q = 0; q < kShapes; ++q)
@@ -620,20 +626,21 @@ struct WalkerMixedT {
         int nev = __builtin_popcount(evm);
         int ax[3];
         event_order(g, m, ax);
-        // Entries of the voxels the events reach if every face passes (the
-        // common case), loaded together so the step waits for memory once
-        // rather than once per event.
+        // Offsets and entries of the voxels the events reach if every face
+        // passes (the common case), loaded together so the step waits for
+        // memory once rather than once per event.
         const int nev0 = nev;
-        uint32_t rsp[3];  // rsp[k] is set, and read, only for k < nev0
+        uint32_t cpath[3], rsp[3];  // rsp[k] is set, and read, only for k < nev0
         {
             uint32_t c = lb;
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
                 c += static_cast<uint32_t>(pick(sst, ax[k]));
+                cpath[k] = c;
                 if (k < nev0) rsp[k] = entry(lab, c);
             }
         }
-        bool spec = true;  // no reflection yet: rsp holds the entries of the voxels reached
+        bool spec = true;  // every face so far passed: cpath and rsp hold the voxels reached
 
         // gap to axis a's face, and the path length to it (divided out only
         // after a permeation)
@@ -643,7 +650,7 @@ struct WalkerMixedT {
         };
         const auto face_len = [&](int a) { return face_gap(a) / fabsf(pick(v, a)); };
         float P = 0.0f, tau = 1.0f;
-        uint32_t passed = 0, refl = 0;
+        uint32_t done = 0, refl = 0;  // axes whose face the step reached; those it reflected at
         uint32_t rawc = 0;  // entry of the voxel last passed into (its halo flags)
         int mw_used = 0;
         uint4 mw;  // words of substream 3, computed before the second membrane hit reads them
@@ -651,11 +658,15 @@ struct WalkerMixedT {
         for (int k = 0; k < 3; ++k) {
             if (k < nev) {
                 const int a = ax[k];
-                ++nface;
-                const uint32_t nbk = lb + static_cast<uint32_t>(pick(sst, a));
-                uint32_t raw;
-                if (spec && k < nev0) raw = rsp[k];
-                else raw = entry(lab, nbk);
+                done |= 1u << a;
+                uint32_t nbk, raw;
+                if (spec && k < nev0) {
+                    nbk = cpath[k];
+                    raw = rsp[k];
+                } else {  // after a reflection, or a face a permeation brought in
+                    nbk = lb + static_cast<uint32_t>(pick(sst, a));
+                    raw = entry(lab, nbk);
+                }
                 const int nl = static_cast<int>(raw & LabelBits<LabelT>::kMask);
                 bool cross = true;
                 if (nl != l) {
@@ -679,12 +690,12 @@ struct WalkerMixedT {
                         ++nperm;
                         const float ek = fmaxf(face_len(a), P);
                         const float dtau = fminf((ek - P) / sig, tau);
-                        R += static_cast<double>(static_cast<float>(p.dt) * dtau * it2);
+                        R += static_cast<double>(dtau * dti2);
                         tau -= dtau;
                         P = ek;
                         l = nl;
                         sig = p.sigma_f[nl];
-                        it2 = p.inv_t2_f[nl];
+                        dti2 = static_cast<float>(p.dt) * p.inv_t2_f[nl];
                         // the later faces, in order, that lie inside the new budget:
                         // face_len < pend compared as gap < pend |v| (no division)
                         const float pend = fmaf(tau, sig, P);
@@ -696,7 +707,6 @@ struct WalkerMixedT {
                     }
                 }
                 if (cross) {
-                    passed |= 1u << a;
                     lb = nbk;
                     rawc = raw;
                 } else {
@@ -705,11 +715,13 @@ struct WalkerMixedT {
                 }
             }
         }
+        const uint32_t passed = done & ~refl;
+        nface += __builtin_popcount(done);
         const uint32_t halo = rawc >> LabelBits<LabelT>::kShift;
         if (__builtin_expect(halo != 0u, 0))
             lb = wrap_halo(p, lb, halo, posm, static_cast<int>(sizeof(LabelT)));
         const float lend = fmaf(tau, sig, P);
-        R += static_cast<double>(static_cast<float>(p.dt) * tau * it2);
+        R += static_cast<double>(tau * dti2);
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
             const bool pos = (posm >> a) & 1u;

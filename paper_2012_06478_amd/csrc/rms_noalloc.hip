@@ -75,7 +75,7 @@ extern "C" int rms_run_noalloc(const rms_substrate* sub, const rms_params* param
     if (e != hipSuccess) return rms::hip_fail("hipGetDevice", e);
     struct DeviceGuard {
         int prev;
-        ~DeviceGuard() { hipSetDevice(prev); }
+        ~DeviceGuard() { (void)hipSetDevice(prev); }
     } guard{prev_dev};
     if ((e = hipSetDevice(sub->device)) != hipSuccess) return rms::hip_fail("hipSetDevice", e);
 

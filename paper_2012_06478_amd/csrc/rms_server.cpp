@@ -121,7 +121,7 @@ template <typename T>
 hipError_t grow(T** p, size_t* cap, size_t need, hipStream_t s) {
     if (need <= *cap) return hipSuccess;
     if (*p) {
-        hipFreeAsync(*p, s);
+        (void)hipFreeAsync(*p, s);
         *p = nullptr;
     }
     const size_t n = std::max<size_t>(need, 2 * *cap);
@@ -137,7 +137,7 @@ hipError_t grow(T** p, size_t* cap, size_t need, hipStream_t s) {
 // Stream-ordered release of a request's device memory (behind every launch
 // already enqueued that reads it).
 void rms_server::free_device(Request* r) {
-    for (void* p : r->dev.ptrs) hipFreeAsync(p, stream);
+    for (void* p : r->dev.ptrs) (void)hipFreeAsync(p, stream);
     r->dev.ptrs.clear();
 }
 
@@ -279,7 +279,7 @@ void rms_server::complete_slice(Slice& sl) {
 }
 
 void rms_server::loop() {
-    hipSetDevice(device);
+    (void)hipSetDevice(device);
     std::deque<Slice> inflight;
     std::vector<Request*> admit;
     for (;;) {
@@ -373,8 +373,8 @@ int rms_server_create(size_t mem_budget_bytes, int slice_steps, rms_server** out
     if (e != hipSuccess) {
         const int rc = rms::hip_fail("server setup", e);
         for (hipEvent_t ev : s->events)
-            if (ev) hipEventDestroy(ev);
-        if (s->stream) hipStreamDestroy(s->stream);
+            if (ev) (void)hipEventDestroy(ev);
+        if (s->stream) (void)hipStreamDestroy(s->stream);
         delete s;
         return rc;
     }
@@ -475,15 +475,15 @@ void rms_server_destroy(rms_server* srv) {
         srv->cv_work.notify_all();
     }
     if (srv->worker.joinable()) srv->worker.join();
-    hipSetDevice(srv->device);
+    (void)hipSetDevice(srv->device);
     for (WorkBuffer& wb : srv->bufs) {
-        if (wb.items) hipFreeAsync(wb.items, srv->stream);
-        if (wb.plans) hipFreeAsync(wb.plans, srv->stream);
+        if (wb.items) (void)hipFreeAsync(wb.items, srv->stream);
+        if (wb.plans) (void)hipFreeAsync(wb.plans, srv->stream);
     }
-    hipStreamSynchronize(srv->stream);
-    for (double* h : srv->pinned_all) hipHostFree(h);
-    for (hipEvent_t ev : srv->events) hipEventDestroy(ev);
-    hipStreamDestroy(srv->stream);
+    (void)hipStreamSynchronize(srv->stream);
+    for (double* h : srv->pinned_all) (void)hipHostFree(h);
+    for (hipEvent_t ev : srv->events) (void)hipEventDestroy(ev);
+    (void)hipStreamDestroy(srv->stream);
     delete srv;
 }
 
