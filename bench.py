@@ -509,6 +509,9 @@ def main():
     ap.add_argument("--workload", choices=WORKLOADS, default="axons")
     ap.add_argument("--walkers", type=int, default=0,
                     help="walker count in place of the workload's (the plain benchmark only)")
+    ap.add_argument("--walk-kernel", choices=("auto", "one", "persistent"), default="auto",
+                    help="walk kernel (rms_set_option RMS_OPT_WALK_KERNEL; auto is the library's "
+                         "choice), for measurements of the launch paths")
     ap.add_argument("--cpu-sample-walkers", type=int, default=250_000)
     ap.add_argument("--cpu-1core-walkers", type=int, default=2_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -573,6 +576,9 @@ def main():
         log("[bench] copied 1 GiB three times")
         return
     log(f"[bench] building workload {args.workload}")
+    if args.walk_kernel != "auto":
+        rms.rms_set_option(rms.RMS_OPT_WALK_KERNEL, rms.RMS_WALK_ONE_LAUNCH
+                           if args.walk_kernel == "one" else rms.RMS_WALK_PERSISTENT)
     c = workload(args.workload)
     default_walkers = c["n_walkers"]
     if args.walkers:
@@ -624,7 +630,8 @@ def main():
         "roofline": {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS,
                      "unit": "TOP/s", "frac": achieved / VALU_PEAK_TOPS,
                      "traffic": (traffic_from_profile(c["name"], args.precision)
-                                 if c["n_walkers"] == default_walkers else None),
+                                 if c["n_walkers"] == default_walkers
+                                 and args.walk_kernel == "auto" else None),
                      "kernel": walk_kernel_name(prec == rms.RMS_FP64, c, r["walk_kernel"]),
                      "kernel_ms": kernel_s * 1e3, "ops_per_walker_step": OPS_TOTAL},
         "last_signal_b_max_dir0": [float(r["signal"][0, -1, 0].real),
