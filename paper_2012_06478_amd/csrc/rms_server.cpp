@@ -110,7 +110,7 @@ struct rms_server {
 
     void loop();
     void enqueue_slice(std::deque<Slice>& inflight);
-    void complete_slice(Slice& sl);
+    void complete_oldest(std::deque<Slice>& inflight);
     void finish(Request* r, int rc, const std::string& err);
     void free_device(Request* r);
 };
@@ -254,18 +254,25 @@ void rms_server::enqueue_slice(std::deque<Slice>& inflight) {
     }
 }
 
-void rms_server::complete_slice(Slice& sl) {
+// Completes the oldest slice in flight and drops it.  After a device error
+// every admitted request has failed (their device work is in doubt), so the
+// slices queued behind no longer refer to live requests: they are waited for
+// and dropped as well.
+void rms_server::complete_oldest(std::deque<Slice>& inflight) {
+    Slice& sl = inflight.front();
     hipError_t e = sl.err;
     if (e == hipSuccess) e = hipEventSynchronize(sl.ev_end);
     float ms = 0.0f;
     if (e == hipSuccess) e = hipEventElapsedTime(&ms, sl.ev_begin, sl.ev_end);
     if (e != hipSuccess) {
-        // the device work of every admitted request is in doubt
         const std::string msg = std::string(sl.what.empty() ? "slice" : sl.what) + ": " +
                                 hipGetErrorString(e);
         std::vector<Request*> all_active;
         all_active.swap(active);
         for (Request* r : all_active) finish(r, RMS_E_DEVICE, msg);
+        inflight.pop_front();
+        for (; !inflight.empty(); inflight.pop_front())
+            (void)hipEventSynchronize(inflight.front().ev_end);
         return;
     }
     {
@@ -276,6 +283,7 @@ void rms_server::complete_slice(Slice& sl) {
         active.erase(std::find(active.begin(), active.end(), r));
         finish(r, RMS_OK, "");
     }
+    inflight.pop_front();
 }
 
 void rms_server::loop() {
@@ -335,14 +343,10 @@ void rms_server::loop() {
             continue;
         }
         if (inflight.empty()) continue;
-        complete_slice(inflight.front());
-        inflight.pop_front();
+        complete_oldest(inflight);
     }
     // stopping: let the slices in flight end, then fail whatever is left
-    while (!inflight.empty()) {
-        complete_slice(inflight.front());
-        inflight.pop_front();
-    }
+    while (!inflight.empty()) complete_oldest(inflight);
     std::vector<Request*> left;
     {
         std::lock_guard<std::mutex> lk(m);
