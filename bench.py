@@ -224,6 +224,7 @@ def serve(args):
                                      waveform=q["waveform"], dirs=q["dirs"], bvals=q["bvals"],
                                      precision=prec, params=_tissue(nl[q["sub"]], q["kappa"]))
 
+    rms.rms_set_option(rms.RMS_OPT_SERVER_WALKERS, int(args.serve_walkers))
     srv = rms.rms_server_create(0, 0)
     try:
         # capacity: the whole trace as one closed batch (every request queued
@@ -292,7 +293,8 @@ def serve(args):
         "launches": st["launches"] - st0["launches"],
         "max_signal_err_vs_fp64": err,
         "config": {"workload": "16 resident substrates 64^3..400^3 u16, "
-                               f"{len(reqs)} Poisson requests", "precision": args.precision},
+                               f"{len(reqs)} Poisson requests", "precision": args.precision,
+                   "server_walkers": int(args.serve_walkers) or "auto"},
     }
     print(json.dumps(line), flush=True)
 
@@ -521,6 +523,9 @@ def main():
                     help="continuous-batching benchmark over a Poisson request trace")
     ap.add_argument("--serve-requests", type=int, default=256)
     ap.add_argument("--serve-load", type=float, default=0.7)
+    ap.add_argument("--serve-walkers", type=float, default=0,
+                    help="walker slots of the server (rms_set_option RMS_OPT_SERVER_WALKERS; "
+                         "0: the library's automatic cap)")
     ap.add_argument("--serve-check", type=int, default=8,
                     help="requests re-run in fp64 to report the served signal error")
     ap.add_argument("--records", type=int, default=0,

@@ -182,10 +182,10 @@ int rms_abi_version(void);
 /* Description of the last failure on the calling thread ("" if none). */
 const char* rms_last_error(void);
 
-/* Process-wide options of the walk launch, for measurements and tests of the
- * launch paths (every run afterwards uses them; not thread-safe against runs
- * in flight).  Neither option changes a result: a walker's trajectory depends
- * only on (seed, walker, step).
+/* Process-wide options of the walk launch and the server, for measurements
+ * and tests of the launch paths (every run or server afterwards uses them; not
+ * thread-safe against runs in flight).  No option changes a result: a
+ * walker's trajectory depends only on (seed, walker, step).
  *   RMS_OPT_WALK_KERNEL     RMS_WALK_AUTO (default: the persistent walk when
  *                           the walkers fill between 1.5 and 4.5 rounds of
  *                           resident waves, else one launch),
@@ -197,10 +197,18 @@ const char* rms_last_error(void);
  *                           of the persistent walk makes for the previous
  *                           segment of its walkers before it gives up and the
  *                           run fails with RMS_E_WAIT_GAVE_UP; >= 0, default
- *                           2^20 (about a second).
+ *                           2^20 (about a second);
+ *   RMS_OPT_SERVER_WALKERS  walker slots of the servers created afterwards:
+ *                           the admitted requests of a server hold at most
+ *                           this many walkers together (a larger request is
+ *                           admitted alone); >= 0, default 0 = sixteen
+ *                           rounds of the device's resident waves of the
+ *                           mixed walker (compute units x 4 SIMDs x 6 waves
+ *                           x 64 x 16, 6.3e6 on MI355X).
  * RMS_E_INVALID_ARG for an unknown option or value. */
 #define RMS_OPT_WALK_KERNEL 1
 #define RMS_OPT_SEG_POLL_LIMIT 2
+#define RMS_OPT_SERVER_WALKERS 3
 int rms_set_option(int option, int64_t value);
 
 /* Build a device-resident substrate (sections 2.1.1 and 2.2 item 1).

@@ -36,6 +36,7 @@ RMS_WALK_PERSISTENT = 1
 RMS_WALK_PACKED = 2
 RMS_OPT_WALK_KERNEL = 1
 RMS_OPT_SEG_POLL_LIMIT = 2
+RMS_OPT_SERVER_WALKERS = 3
 RMS_E_WAIT_GAVE_UP = -10
 ERROR_NAMES = {
     -1: "RMS_E_INVALID_ARG", -2: "RMS_E_LABEL_RANGE", -3: "RMS_E_STEP_TOO_LARGE",
@@ -169,7 +170,8 @@ def rms_last_error() -> str:
 
 
 def rms_set_option(option: int, value: int) -> None:
-    """Process-wide launch option (``RMS_OPT_WALK_KERNEL``, ``RMS_OPT_SEG_POLL_LIMIT``)."""
+    """Process-wide option (``RMS_OPT_WALK_KERNEL``, ``RMS_OPT_SEG_POLL_LIMIT``,
+    ``RMS_OPT_SERVER_WALKERS``)."""
     _check(_load().rms_set_option(int(option), int(value)))
 
 

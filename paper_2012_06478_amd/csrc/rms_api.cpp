@@ -787,6 +787,11 @@ int rms_set_option(int option, int64_t value) {
                                                     "RMS_WALK_ONE_LAUNCH or RMS_WALK_PERSISTENT");
             rms::set_walk_choice(static_cast<int>(value));
             return RMS_OK;
+        case RMS_OPT_SERVER_WALKERS:
+            if (value < 0)
+                return rms::fail(RMS_E_INVALID_ARG, "RMS_OPT_SERVER_WALKERS: >= 0 (0: automatic)");
+            rms::set_server_walkers(value);
+            return RMS_OK;
         case RMS_OPT_SEG_POLL_LIMIT:
             if (value < 0 || value > int64_t(0xFFFFFFFEu))
                 return rms::fail(RMS_E_INVALID_ARG, "RMS_OPT_SEG_POLL_LIMIT: 0 .. 2^32 - 2 polls");

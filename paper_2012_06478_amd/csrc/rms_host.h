@@ -111,6 +111,10 @@ struct DeviceRun {
 int execute_run(const RunSetup& r, DeviceRun& dr, hipStream_t stream, hipEvent_t ev0,
                 hipEvent_t ev1, std::chrono::steady_clock::time_point t0, rms_result* out);
 
+// Walker slots of servers created afterwards (RMS_OPT_SERVER_WALKERS; 0:
+// automatic).
+void set_server_walkers(int64_t walkers);
+
 // Copies the reduced results (device layout of ReducePlan::result) into the
 // caller's rms_result.
 void fill_result(const RunSetup& r, const double* res, rms_result* out);

@@ -24,6 +24,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
@@ -47,6 +48,23 @@ double seconds_since(clock_type::time_point t0, clock_type::time_point t) {
 
 // Slices in flight at once: the one running and the one queued behind it.
 constexpr int kDepth = 2;
+
+// RMS_OPT_SERVER_WALKERS (0: automatic), read when a server is created.
+std::atomic<int64_t> g_server_walkers{0};
+
+// Automatic walker slots: sixteen rounds of the resident waves of the mixed
+// walker (six per SIMD).  With every queued request admitted, the slices
+// shrink to their 64-step minimum and their walkers read the labels of many
+// substrates; with a cap, a slice is long enough that moving the walker
+// states between slices costs little, while every launch still fills the
+// device.
+int64_t auto_walker_slots(int device) {
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess ||
+        cus <= 0)
+        cus = 256;
+    return int64_t(cus) * 4 * 6 * 64 * 16;
+}
 // Largest result record of a request: kAccFixed + 2 n_sig + 2 n_dirs doubles.
 constexpr size_t kResMax = rms::kAccFixed + 2 * RMS_MAX_SIGNALS + 2 * RMS_MAX_SIGNALS;
 
@@ -57,6 +75,7 @@ struct Request {
     size_t bytes = 0;
     int64_t steps_sched = 0;   // steps enqueued on the device
     bool last_sched = false;   // the slice with its last steps is enqueued
+    bool admitted = false;     // holds walker slots and memory of the budget
     double* h_res = nullptr;   // pinned block its results are copied to
     enum State { kPending, kActive, kDone, kFailed } state = kPending;
     int rc = RMS_OK;
@@ -91,6 +110,7 @@ struct rms_server {
     hipStream_t stream = nullptr;
     hipEvent_t events[2 * kDepth] = {};
     size_t budget = 0, in_use = 0;
+    int64_t walker_slots = 0, walkers_in_use = 0;  // of the admitted requests
     int slice_steps = 0;
     std::mutex m;
     std::condition_variable cv_work, cv_done;
@@ -150,7 +170,11 @@ void rms_server::finish(Request* r, int rc, const std::string& err) {
         r->h_res = nullptr;
     }
     std::lock_guard<std::mutex> lk(m);
-    in_use -= r->bytes;
+    if (r->admitted) {  // requests still pending at destruction hold nothing
+        in_use -= r->bytes;
+        walkers_in_use -= r->setup.n_walkers;
+        r->admitted = false;
+    }
     r->rc = rc;
     r->err = err;
     r->t_done = clock_type::now();
@@ -296,10 +320,16 @@ void rms_server::loop() {
             if (inflight.empty() && active.empty())
                 cv_work.wait(lk, [&] { return stop || !pending.empty(); });
             if (stop) break;
-            while (!pending.empty() && in_use + pending.front()->bytes <= budget) {
+            // in arrival order, while the memory budget and the walker slots
+            // hold them (a request larger than all the slots runs alone)
+            while (!pending.empty() && in_use + pending.front()->bytes <= budget &&
+                   (walkers_in_use == 0 ||
+                    walkers_in_use + pending.front()->setup.n_walkers <= walker_slots)) {
                 Request* r = pending.front();
                 pending.pop_front();
                 in_use += r->bytes;
+                walkers_in_use += r->setup.n_walkers;
+                r->admitted = true;
                 admit.push_back(r);
             }
         }
@@ -358,6 +388,12 @@ void rms_server::loop() {
     for (Request* r : left) finish(r, RMS_E_INVALID_ARG, "server destroyed before completion");
 }
 
+namespace rms {
+void set_server_walkers(int64_t walkers) {
+    g_server_walkers.store(walkers, std::memory_order_relaxed);
+}
+}  // namespace rms
+
 extern "C" {
 
 int rms_server_create(size_t mem_budget_bytes, int slice_steps, rms_server** out) {
@@ -383,6 +419,8 @@ int rms_server_create(size_t mem_budget_bytes, int slice_steps, rms_server** out
         return rc;
     }
     s->budget = mem_budget_bytes ? mem_budget_bytes : free_b / 4 * 3;
+    const int64_t w = g_server_walkers.load(std::memory_order_relaxed);
+    s->walker_slots = w > 0 ? w : auto_walker_slots(s->device);
     s->slice_steps = (slice_steps + 3) / 4 * 4;
     s->worker = std::thread([s] { s->loop(); });
     *out = s;

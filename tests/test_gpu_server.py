@@ -182,6 +182,33 @@ def test_admission_by_memory(substrates):
         _same(got, rms.rms_run(s, **kw))
 
 
+def test_admission_by_walker_slots(substrates):
+    """With 4000 walker slots the 3000- and 700-walker requests share them and
+    the 10 000-walker request (more than all the slots) runs alone, after both
+    have finished; every result is still exact, and the option returns to
+    automatic."""
+    reqs = _requests(substrates)[:3]
+    print("[case] admission by walker slots", flush=True)
+    rms.rms_set_option(rms.RMS_OPT_SERVER_WALKERS, 4000)
+    try:
+        srv = rms.rms_server_create(0, 512)
+    finally:
+        rms.rms_set_option(rms.RMS_OPT_SERVER_WALKERS, 0)
+    try:
+        tickets = [rms.rms_server_submit(srv, s, **kw) for s, kw in reqs]
+        results = [rms.rms_server_wait(srv, t, shape, 120.0) for t, shape in tickets]
+        st = rms.rms_server_stats_get(srv)
+    finally:
+        rms.rms_server_destroy(srv)
+    assert st["completed"] == 3 and st["bytes_in_use"] == 0
+    done_first_two = max(results[0]["wall_s"], results[1]["wall_s"])
+    assert results[2]["queue_s"] >= done_first_two - 0.05
+    for (s, kw), got in zip(reqs, results):
+        _same(got, rms.rms_run(s, **kw))
+    with pytest.raises(rms.RmsError):
+        rms.rms_set_option(rms.RMS_OPT_SERVER_WALKERS, -1)
+
+
 def test_server_errors(substrates):
     srv = rms.rms_server_create(1_000_000, 0)
     try:

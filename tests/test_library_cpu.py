@@ -93,7 +93,7 @@ def test_set_option_validates_without_a_device():
     rms.rms_set_option(rms.RMS_OPT_SEG_POLL_LIMIT, 1 << 20)
     text = open(os.path.join(ROOT, "include", "rms.h")).read()
     for name in ("RMS_WALK_ONE_LAUNCH", "RMS_WALK_PERSISTENT", "RMS_WALK_PACKED",
-                 "RMS_OPT_WALK_KERNEL", "RMS_OPT_SEG_POLL_LIMIT"):
+                 "RMS_OPT_WALK_KERNEL", "RMS_OPT_SEG_POLL_LIMIT", "RMS_OPT_SERVER_WALKERS"):
         assert getattr(rms, name) == int(re.search(rf"#define {name} (\d+)", text).group(1))
     assert rms.ERROR_NAMES[rms.RMS_E_WAIT_GAVE_UP] == "RMS_E_WAIT_GAVE_UP"
     assert int(re.search(r"#define RMS_E_WAIT_GAVE_UP \((-\d+)\)", text).group(1)) == -10
