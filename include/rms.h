@@ -240,7 +240,7 @@ void rms_destroy_substrate(rms_substrate* sub);
  *                substrate defaults; n_labels must match);
  *   seed         64-bit key of the counter-based random streams: walker w's
  *                trajectory depends only on (seed, w, substrate, params, dt);
- *   n_walkers    >= 1; n_steps in [0, 2^32 - 2]; dt_ms > 0;
+ *   n_walkers    in [1, 2^32 - 2]; n_steps in [0, 2^32 - 2]; dt_ms > 0;
  *   n_shapes     0..RMS_MAX_SHAPES gradient shapes; waveform is
  *                [n_shapes][n_steps], sample i applies during step i+1, each
  *                shape balanced (sum of samples ~ 0);

@@ -195,7 +195,11 @@ int prepare_run(const rms_substrate* sub, const rms_params* params, uint64_t see
                 const double* bvals, int precision, RunSetup& r) {
     if (!sub) return fail(RMS_E_INVALID_ARG, "substrate is required");
     if (n_walkers < 1) return fail(RMS_E_INVALID_ARG, "n_walkers must be >= 1");
-    if (n_walkers > (int64_t(1) << 40)) return fail(RMS_E_INVALID_ARG, "n_walkers too large");
+    // walker indices are 32-bit (the high counter word of every stream is 0;
+    // 2^32 - 1 marks an empty thread slot); the records alone of that many
+    // walkers would need more than the device's memory
+    if (n_walkers > 0xFFFFFFFELL)
+        return fail(RMS_E_INVALID_ARG, "n_walkers must be in [1, 2^32 - 2]");
     if (n_steps < 0 || n_steps > 0xFFFFFFFELL)
         return fail(RMS_E_INVALID_ARG, "n_steps must be in [0, 2^32 - 2]");
     if (!(dt_ms > 0.0) || !std::isfinite(dt_ms)) return fail(RMS_E_INVALID_ARG, "dt must be > 0");
@@ -271,7 +275,7 @@ int prepare_run(const rms_substrate* sub, const rms_params* params, uint64_t see
     // discrete b of a unit shape is dt sum_k Q_k^2 (section 2.3, Eq. signal)
     r.b_disc.assign(n_shapes, 0.0);
     std::vector<double> kscale(static_cast<size_t>(n_shapes) * n_b, 0.0);
-    r.trig.resize(2 * kTrigSize);
+    r.trig.resize(kTrigSize + 1);
     fill_trig_table(r.trig.data());
     r.gdt.assign(static_cast<size_t>(n_shapes) * n_steps, 0.0);
     for (int s = 0; s < n_shapes; ++s) {
@@ -414,7 +418,7 @@ RunLayout run_layout(const rms_substrate& sub, const RunSetup& r, bool resumable
     o.accept = take(r.accept.size() * sizeof(uint64_t));
     o.start_try = take(r.accept.empty() ? 0 : static_cast<size_t>(r.n_walkers) * sizeof(uint32_t));
     o.gdt = take(r.gdt.size() * sizeof(double));
-    o.trig = take(2 * kTrigSize * sizeof(double));
+    o.trig = take((kTrigSize + 1) * sizeof(double2));
     o.wstate = take(static_cast<size_t>(r.n_walkers) * r.width * sizeof(double));
     o.kg = take(r.kg.size() * sizeof(double));
     o.sig_shape = take(r.sig_shape.size() * sizeof(int));
@@ -465,7 +469,7 @@ int DeviceRun::bind(const rms_substrate& sub, const RunSetup& r, bool resumable,
     uint32_t* d_start_try =
         r.accept.empty() ? nullptr : reinterpret_cast<uint32_t*>(b + o.start_try);
     double* d_gdt = reinterpret_cast<double*>(b + o.gdt);
-    double* d_trig = reinterpret_cast<double*>(b + o.trig);
+    double2* d_trig = reinterpret_cast<double2*>(b + o.trig);
     double* d_wstate = reinterpret_cast<double*>(b + o.wstate);
     double* d_kg = reinterpret_cast<double*>(b + o.kg);
     int* d_sig_shape = reinterpret_cast<int*>(b + o.sig_shape);

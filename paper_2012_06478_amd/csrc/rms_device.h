@@ -59,6 +59,8 @@ __device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
     return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
 }
 
+// The counter words of Philox4x32-10 as the walkers use them: (index,
+// substream, walker, high word) with key (k0, k1) = the seed.
 __device__ __forceinline__ uint4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2,
                                                uint32_t c3, uint32_t k0, uint32_t k1) {
 #pragma unroll
@@ -67,6 +69,41 @@ __device__ __forceinline__ uint4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_
         const uint64_t p1 = static_cast<uint64_t>(0xCD9E8D57u) * c2;
         const uint32_t n0 = xor3(static_cast<uint32_t>(p1 >> 32), c1, k0);
         const uint32_t n2 = xor3(static_cast<uint32_t>(p0 >> 32), c3, k1);
+        c1 = static_cast<uint32_t>(p1);
+        c3 = static_cast<uint32_t>(p0);
+        c0 = n0;
+        c2 = n2;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return make_uint4(c0, c1, c2, c3);
+}
+
+// The same generator for counters whose index and substream are the same
+// across the wave and whose high word is 0: the first round's n2 and p0 and
+// the second round's p1 and c3 are then wave-uniform, and the xors of those
+// two rounds pair the uniform terms first, so that the compiler keeps them
+// in scalar registers and each vector result costs one instruction (a vector
+// instruction reads at most one scalar register).
+__device__ __forceinline__ uint4 philox4x32_10_uniform(uint32_t c0, uint32_t c1, uint32_t c2,
+                                                       uint32_t k0, uint32_t k1) {
+    uint32_t c3 = 0u;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t p0 = static_cast<uint64_t>(0xD2511F53u) * c0;
+        const uint64_t p1 = static_cast<uint64_t>(0xCD9E8D57u) * c2;
+        const uint32_t h0 = static_cast<uint32_t>(p0 >> 32), h1 = static_cast<uint32_t>(p1 >> 32);
+        uint32_t n0, n2;
+        if (r == 0) {
+            n0 = h1 ^ (c1 ^ k0);
+            n2 = (h0 ^ c3) ^ k1;
+        } else if (r == 1) {
+            n0 = c1 ^ (h1 ^ k0);
+            n2 = h0 ^ (c3 ^ k1);
+        } else {
+            n0 = xor3(h1, c1, k0);
+            n2 = xor3(h0, c3, k1);
+        }
         c1 = static_cast<uint32_t>(p1);
         c3 = static_cast<uint32_t>(p0);
         c0 = n0;
@@ -94,24 +131,29 @@ struct FmaSgpr {
     }
 };
 
-// cos(2 pi u) and sin(2 pi u) for u = (w + 1/2) 2^-32, within a few ulp.  The
-// top eight bits of w pick the angle A = 2 pi j / 256 from `tab` (cos A, sin
-// A); the rest is a = 2 pi (w mod 2^24 + 1/2) 2^-32 in (0, 2 pi / 256), whose
-// sine and cosine are the Taylor series through a^7 and a^6 (the next terms
-// are below 1e-17 there), evaluated by Horner's rule in a^2; the angle-sum
-// formulas combine the two.  `fk` is the fused multiply-add used for the
+// 2 cos(2 pi u) and 2 sin(2 pi u) for u = (w + 1/2) 2^-32, within a few ulp
+// (the factor 2 of the direction's transverse length comes from the table,
+// exactly).  The top eight bits of w pick the angle A = 2 pi j / 256, whose
+// (2 cos A, 2 sin A) `tab` holds as one 16-byte entry; the rest is
+// a = 2 pi (w mod 2^24 + 1/2) 2^-32 in (0, 2 pi / 256), whose sine and cosine
+// are the Taylor series through a^7 and a^6 (the next terms are below 1e-17
+// there), evaluated by Horner's rule in a^2; the angle-sum formulas combine
+// the two.  `lead` holds the series' leading coefficients (-1/7!, -1/6!),
+// kLeadCoefficients: the walker reads them from LDS at each step rather than
+// keeping them in registers.  `fk` is the fused multiply-add used for the
 // Horner steps (its third operand is a coefficient).
 template <class Fma>
-__host__ __device__ __forceinline__ void sincos_2pi_word(uint32_t w, const double* tab,
-                                                         double* s_out, double* c_out, Fma fk) {
-    const uint32_t j = w >> 24;
-    const double cA = tab[2 * j], sA = tab[2 * j + 1];
+__host__ __device__ __forceinline__ void sincos_2pi_word(uint32_t w, const double2* tab,
+                                                         double2 lead, double* s_out,
+                                                         double* c_out, Fma fk) {
+    const double2 e = tab[w >> 24];
+    const double cA = e.x, sA = e.y;
     const double a = (static_cast<double>(w & 0xFFFFFFu) + 0.5) * (6.283185307179586 * 0x1p-32);
     const double z = a * a;
-    double ps = fk(z, -1.0 / 5040.0, 1.0 / 120.0);  // sin a = a (1 - z/3! + z^2/5! - z^3/7!)
+    double ps = fk(z, lead.x, 1.0 / 120.0);  // sin a = a (1 - z/3! + z^2/5! - z^3/7!)
     ps = fk(z, ps, -1.0 / 6.0);
     const double sa = fma(a * z, ps, a);
-    double pc = fk(z, -1.0 / 720.0, 1.0 / 24.0);    // cos a = 1 - z/2! + z^2/4! - z^3/6!
+    double pc = fk(z, lead.y, 1.0 / 24.0);   // cos a = 1 - z/2! + z^2/4! - z^3/6!
     pc = fma(z, pc, -0.5);
     const double ca = fma(z, pc, 1.0);
     *c_out = fma(cA, ca, -(sA * sa));
@@ -136,6 +178,20 @@ __device__ __forceinline__ double sqrt_pos(double y) {
 struct Ids {
     uint32_t wlo, whi, k0, k1;
 };
+
+// Identity of walker w (below 2^32 - 1: the host refuses larger runs, so the
+// high counter word is 0) under the given seed.  Walkers with
+// kUniformCounters take the high word as the constant 0 and walk with the
+// streams specialised for it (philox4x32_10_uniform); the double-precision
+// walker takes it as w >> 32, which the compiler cannot prove 0 where the
+// walker index is 64 bits wide: specialised, it ran 2% slower on the 200^3
+// packing (and, before its series coefficients moved to LDS, spilled).
+template <class Walker>
+__device__ __forceinline__ Ids walker_ids(int64_t w, uint64_t seed) {
+    const uint32_t hi = Walker::kUniformCounters ? 0u : static_cast<uint32_t>(w >> 32);
+    return Ids{static_cast<uint32_t>(w), hi, static_cast<uint32_t>(seed),
+               static_cast<uint32_t>(seed >> 32)};
+}
 
 // Block of substream 3 for step index i0: the second and third membrane words
 // of the step.  Few steps hit a membrane twice, so the block is computed only
@@ -344,6 +400,8 @@ struct WalkerF64T {
     // absorbing form holds four more words per step and is given four
     static constexpr int kWaves = MT ? 4 : 5;
     static constexpr bool kMT = MT;
+    // streams specialised for a zero high counter word (walker_ids)
+    static constexpr bool kUniformCounters = false;
     uint32_t lb;     // byte offset of the voxel's entry in the padded volume
     int l, l0;       // label, label at the start
     uint32_t nface, nhit, nperm;
@@ -375,15 +433,25 @@ struct WalkerF64T {
     __device__ __forceinline__ void step(const WalkPlan& p, const LabelT* __restrict__ lab,
                                          uint32_t i0, uint32_t wa, uint32_t wb, uint32_t m1,
                                          [[maybe_unused]] uint32_t t1,
-                                         const Ids& id, const double* trig) {
+                                         const Ids& id, const double2* trig) {
         const double u1 = unit_open(wa);
-        double sn, cs;  // of 2 pi u2, u2 = unit_open(wb)
-        sincos_2pi_word(wb, trig, &sn, &cs, FmaSgpr());
-        const double rho = 2.0 * sqrt_pos(u1 * (1.0 - u1));
-        const double v[3] = {rho * cs, rho * sn, 1.0 - 2.0 * u1};
+        double sn2, cs2;  // 2 sin and 2 cos of 2 pi u2, u2 = unit_open(wb)
+        // the series' leading coefficients from the LDS entry behind the angle
+        // table, read at every step (volatile): held in registers across
+        // steps they would take four of the walker's 96
+        using LdsDouble = const volatile __attribute__((address_space(3))) double;
+        LdsDouble* lv = (LdsDouble*)(trig + kTrigSize);
+        double2 lead;
+        lead.x = lv[0];
+        lead.y = lv[1];
+        sincos_2pi_word(wb, trig, lead, &sn2, &cs2, FmaSgpr());
+        // transverse length 2 sqrt(u1 (1 - u1)); the 2 is in cs2 and sn2
+        const double sq = sqrt_pos(u1 * (1.0 - u1));
+        const double v[3] = {sq * cs2, sq * sn2, 1.0 - 2.0 * u1};
 
-        // per axis: gap to the face the step moves toward and |v|; a face lies
-        // inside the budget sig when gap < sig |v|
+        // per axis: the gap |F - o| to the face the step moves toward (F = 1
+        // moving up, else 0; o stays in [0, 1]) and |v|; a face lies inside
+        // the budget sig when gap < sig |v|
         double g[3], m[3];
         uint32_t posm = 0, evm = 0;
         int sst[3];  // byte step in the padded volume across the face each axis moves toward
@@ -394,7 +462,7 @@ struct WalkerF64T {
             sst[a] = pos ? st : -st;
             posm |= pos ? (1u << a) : 0u;
             m[a] = fabs(v[a]);
-            g[a] = pos ? 1.0 - o[a] : o[a];  // o stays in [0, 1]
+            g[a] = fabs((pos ? 1.0 : 0.0) - o[a]);
             evm |= g[a] < sig * m[a] ? (1u << a) : 0u;
         }
         int nev = __builtin_popcount(evm);
@@ -566,6 +634,8 @@ struct WalkerMixedT {
     // spill); the absorbing form holds four more words per step and is given five
     static constexpr int kWaves = MT ? 5 : 6;
     static constexpr bool kMT = MT;
+    // streams specialised for a zero high counter word (walker_ids)
+    static constexpr bool kUniformCounters = true;
     uint32_t lb;  // byte offset of the voxel's entry in the padded volume
     int l, l0;
     uint32_t nface, nhit, nperm;
@@ -599,7 +669,7 @@ struct WalkerMixedT {
     __device__ __forceinline__ void step(const WalkPlan& p, const LabelT* __restrict__ lab,
                                          uint32_t i0, uint32_t wa, uint32_t wb, uint32_t m1,
                                          [[maybe_unused]] uint32_t t1,
-                                         const Ids& id, const double* trig) {
+                                         const Ids& id, const double2* trig) {
         // uniform deviates from the top 24 bits of each word: (k + 1/2) 2^-24
         const float u1 = fmaf(static_cast<float>(wa >> 8), 0x1p-24f, 0x1p-25f);
         const float u2 = fmaf(static_cast<float>(wb >> 8), 0x1p-24f, 0x1p-25f);
@@ -776,38 +846,41 @@ using WalkerMixed = WalkerMixedT<LabelT, NS, false>;
 template <typename LabelT, int NS>
 using WalkerMixedMT = WalkerMixedT<LabelT, NS, true>;
 
-// Steps [b, e) of one walker: direction words two steps per Philox block,
-// first membrane words four steps per block, both blocks computed under
-// wave-uniform branches at the step that opens them.  With kAnyStart false, b
-// is a multiple of 4 (step 0, a segment of the persistent walk or a server
-// slice); with kAnyStart true (a walk resumed after a record step) a range
-// that starts inside a block first computes the blocks its first steps read.
-// One step per iteration keeps consecutive steps from being interleaved by the
-// scheduler, which would raise register use.
+// Steps [b, e) of one walker, two steps (one direction block) per iteration,
+// each taking its direction words from fixed fields of the block (a range
+// that starts or ends inside a pair skips the step outside it under a
+// wave-uniform test); the first-membrane block (four steps) is computed by
+// the iterations that open one and by the first.  A scheduling barrier
+// between the steps keeps them from being interleaved, which would raise
+// register use.  kAnyStart false: b is a multiple of 4 (step 0, a segment of
+// the persistent walk or a server slice); true: any b (a walk resumed after a
+// record step).
 template <bool kAnyStart = false, class Walker, typename LabelT>
 __device__ __forceinline__ void walk_range(const WalkPlan& p, const LabelT* __restrict__ lab,
                                            Walker& W, uint32_t b, uint32_t e, const Ids& id,
-                                           const double* trig) {
-    uint4 wd = make_uint4(0, 0, 0, 0), wm = make_uint4(0, 0, 0, 0);
+                                           const double2* trig) {
+    const auto block = [&](uint32_t index, uint32_t substream) {
+        if constexpr (Walker::kUniformCounters)
+            return philox4x32_10_uniform(index, substream, id.wlo, id.k0, id.k1);
+        else
+            return philox4x32_10(index, substream, id.wlo, id.whi, id.k0, id.k1);
+    };
+    uint4 wm = make_uint4(0, 0, 0, 0);
     [[maybe_unused]] uint4 wt = make_uint4(0, 0, 0, 0);  // saturation words (MT only)
-    if constexpr (kAnyStart) {
-        if (b & 1u) wd = philox4x32_10(b >> 1, 0u, id.wlo, id.whi, id.k0, id.k1);
-        if (b & 3u) wm = philox4x32_10(b >> 2, 1u, id.wlo, id.whi, id.k0, id.k1);
-        if constexpr (Walker::kMT)
-            if (b & 3u) wt = philox4x32_10(b >> 2, 4u, id.wlo, id.whi, id.k0, id.k1);
-    }
-    for (uint32_t i0 = b; i0 < e; ++i0) {
-        const bool odd = (i0 & 1u) != 0;
-        if (!odd) wd = philox4x32_10(i0 >> 1, 0u, id.wlo, id.whi, id.k0, id.k1);
-        const uint32_t q = i0 & 3u;
-        if (q == 0) {
-            wm = philox4x32_10(i0 >> 2, 1u, id.wlo, id.whi, id.k0, id.k1);
-            if constexpr (Walker::kMT) wt = philox4x32_10(i0 >> 2, 4u, id.wlo, id.whi, id.k0, id.k1);
+    const uint32_t first = b & ~1u;
+    for (uint32_t q0 = first; q0 < e; q0 += 2) {
+        if ((q0 & 3u) == 0 || q0 == first) {
+            wm = block(q0 >> 2, 1u);
+            if constexpr (Walker::kMT) wt = block(q0 >> 2, 4u);
         }
-        const uint32_t m1 = q == 0 ? wm.x : (q == 1 ? wm.y : (q == 2 ? wm.z : wm.w));
-        uint32_t t1 = 0u;
-        if constexpr (Walker::kMT) t1 = q == 0 ? wt.x : (q == 1 ? wt.y : (q == 2 ? wt.z : wt.w));
-        W.step(p, lab, i0, odd ? wd.z : wd.x, odd ? wd.w : wd.y, m1, t1, id, trig);
+        const bool hi = (q0 & 2u) != 0;  // the membrane block's third and fourth steps
+        const uint4 wd = block(q0 >> 1, 0u);
+        if (!kAnyStart || q0 >= b)
+            W.step(p, lab, q0, wd.x, wd.y, hi ? wm.z : wm.x, hi ? wt.z : wt.x, id, trig);
+        __builtin_amdgcn_sched_barrier(0);
+        if (q0 + 1 < e)
+            W.step(p, lab, q0 + 1, wd.z, wd.w, hi ? wm.w : wm.y, hi ? wt.w : wt.y, id, trig);
+        __builtin_amdgcn_sched_barrier(0);
     }
 }
 

@@ -31,15 +31,17 @@ struct rms_substrate {
 
 namespace rms {
 
-// (cos, sin) of the angles 2 pi j / kTrigSize, each rounded once from long
-// double: the table of the double-precision direction draw.
-inline void fill_trig_table(double* cs) {
+// (2 cos, 2 sin) of the angles 2 pi j / kTrigSize, each rounded once from
+// long double (the factor 2 is exact), then kLeadCoefficients: the table of
+// the double-precision direction draw (kTrigSize + 1 entries).
+inline void fill_trig_table(double2* cs) {
     const long double two_pi = 6.283185307179586476925286766559005768394L;
     for (int j = 0; j < kTrigSize; ++j) {
         const long double t = two_pi * static_cast<long double>(j) / kTrigSize;
-        cs[2 * j] = static_cast<double>(cosl(t));
-        cs[2 * j + 1] = static_cast<double>(sinl(t));
+        cs[j].x = 2.0 * static_cast<double>(cosl(t));
+        cs[j].y = 2.0 * static_cast<double>(sinl(t));
     }
+    cs[kTrigSize] = kLeadCoefficients;
 }
 
 // Stream-ordered device allocation from the library's own pool on the
@@ -69,7 +71,7 @@ struct RunSetup {
     std::vector<uint64_t> accept;  // start acceptance per label (spin concentrations), or empty
     double max_sigma = 0.0, max_p = 0.0;
     std::vector<double> gdt;
-    std::vector<double> trig;  // [kTrigSize][2] angle table (fill_trig_table)
+    std::vector<double2> trig;  // [kTrigSize + 1] angle table (fill_trig_table)
     std::vector<double> b_disc, kg, unit;
     std::vector<int> sig_shape;
 };

@@ -52,7 +52,8 @@ struct WalkPlan {
     double voxel_um;
     int n_shapes;
     const double* gdt;   // [n_shapes][n_steps] dt * G_s[i]
-    const double* trig;  // [kTrigSize][2] cos, sin of 2 pi j / kTrigSize (fill_trig_table)
+    const double2* trig; // [kTrigSize + 1] 2 cos, 2 sin of 2 pi j / kTrigSize, then the
+                         // series' leading coefficients (fill_trig_table)
     double* wstate;      // [n_walkers][kDumpFixed + 3 n_shapes] per-walker results
     void* state;         // [n_walkers] resumable walker states (packed launches), or null
     uint32_t* order;     // [n_slots] walker of each thread slot (kNoWalker: none), or
@@ -66,8 +67,11 @@ struct WalkPlan {
 
 constexpr uint32_t kNoWalker = 0xFFFFFFFFu;
 
-// Angles of the direction table: (cos, sin) of 2 pi j / kTrigSize.
+// Angles of the direction table: (2 cos, 2 sin) of 2 pi j / kTrigSize,
+// followed by one entry holding the leading coefficients (-1/7!, -1/6!) of
+// the sine and cosine series of the remainder angle.
 constexpr int kTrigSize = 256;
+constexpr double2 kLeadCoefficients = {-1.0 / 5040.0, -1.0 / 720.0};
 
 // Control words of the persistent walk: eight queue heads, then the flag a
 // block sets when a wait for an earlier segment gives up.

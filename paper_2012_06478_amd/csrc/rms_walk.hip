@@ -3,8 +3,10 @@
 // walk_kernel         one run: lane = walker, all steps in registers, then the
 //                     per-walker record.  The only memory traffic inside the
 //                     step loop is the neighbour-label gather at each face a
-//                     step reaches, the wave-uniform waveform sample (scalar
-//                     load) and, at membranes only, the permeation threshold.
+//                     step reaches, the wave-uniform waveform sample and, at
+//                     membranes only, the permeation threshold (the angle
+//                     table and the series coefficients of the direction
+//                     draw come from LDS).
 // walk_packed_kernel  several runs in one launch (the server): block = (run,
 //                     256 walkers, range of steps) from a work list; the walker
 //                     resumes from its stored state and stores it again, so a
@@ -23,8 +25,8 @@ namespace {
 using dev::Ids;
 
 // Waves per SIMD each walker asks for: five for the double-precision walker,
-// which then fits 96 registers (a few bytes of spill outside the step) and
-// runs about 7% faster than at four; six for the mixed walker, which keeps
+// which then fits 96 registers (without spilling up to two waveform shapes)
+// and runs about 7% faster than at four; six for the mixed walker, which keeps
 // it within 80 registers (left free, it grows past 85 with two waveform
 // shapes and drops to five waves, 16% slower).  The absorbing-membrane forms
 // carry four more words per step and ask for one wave fewer: squeezed to the
@@ -33,20 +35,22 @@ using dev::Ids;
 #define RMS_WALK_OCCUPANCY __attribute__((amdgpu_waves_per_eu(Walker::kWaves, 8)))
 
 // The angle table of the double-precision direction draw, copied to LDS by
-// the whole block before any thread leaves (one entry per thread).
+// the whole block before any thread leaves (one 16-byte entry per thread, so
+// a step reads its entry with one LDS load; thread 0 also copies the
+// coefficient entry behind the angles).
 static_assert(kBlock == kTrigSize, "one table entry per thread");
 template <class Walker>
-__device__ __forceinline__ void load_trig(const WalkPlan& p, double* trig) {
+__device__ __forceinline__ void load_trig(const WalkPlan& p, double2* trig) {
     if constexpr (Walker::kTrig) {
-        trig[2 * threadIdx.x] = p.trig[2 * threadIdx.x];
-        trig[2 * threadIdx.x + 1] = p.trig[2 * threadIdx.x + 1];
+        trig[threadIdx.x] = p.trig[threadIdx.x];
+        if (threadIdx.x == 0) trig[kTrigSize] = p.trig[kTrigSize];
         __syncthreads();
     }
 }
 
 template <class Walker, typename LabelT>
 __global__ __launch_bounds__(kBlock) RMS_WALK_OCCUPANCY void walk_kernel(WalkPlan p) {
-    __shared__ double trig[Walker::kTrig ? 2 * kTrigSize : 2];
+    __shared__ double2 trig[Walker::kTrig ? kTrigSize + 1 : 1];
     load_trig<Walker>(p, trig);
     const int64_t slot = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
     int64_t w = slot;
@@ -59,8 +63,7 @@ __global__ __launch_bounds__(kBlock) RMS_WALK_OCCUPANCY void walk_kernel(WalkPla
         return;
     }
     const LabelT* __restrict__ lab = static_cast<const LabelT*>(p.labels);
-    const Ids id{static_cast<uint32_t>(w), static_cast<uint32_t>(w >> 32),
-                 static_cast<uint32_t>(p.seed), static_cast<uint32_t>(p.seed >> 32)};
+    const Ids id = dev::walker_ids<Walker>(w, p.seed);
     Walker W;
     W.init(p, lab, id);
     dev::walk_range(p, lab, W, 0u, static_cast<uint32_t>(p.n_steps), id, trig);
@@ -72,7 +75,7 @@ __global__ __launch_bounds__(kBlock) RMS_WALK_OCCUPANCY void walk_packed_kernel(
                                                              const WalkPlan* __restrict__ plans) {
     const PackedItem it = items[blockIdx.x];
     const WalkPlan p = plans[it.plan];
-    __shared__ double trig[Walker::kTrig ? 2 * kTrigSize : 2];
+    __shared__ double2 trig[Walker::kTrig ? kTrigSize + 1 : 1];
     load_trig<Walker>(p, trig);
     const int64_t slot = it.first_slot + threadIdx.x;
     int64_t w = slot;
@@ -85,18 +88,18 @@ __global__ __launch_bounds__(kBlock) RMS_WALK_OCCUPANCY void walk_packed_kernel(
         return;
     }
     const LabelT* __restrict__ lab = static_cast<const LabelT*>(p.labels);
-    const Ids id{static_cast<uint32_t>(w), static_cast<uint32_t>(w >> 32),
-                 static_cast<uint32_t>(p.seed), static_cast<uint32_t>(p.seed >> 32)};
+    const Ids id = dev::walker_ids<Walker>(w, p.seed);
     Walker* st = static_cast<Walker*>(p.state) + w;
     Walker W;
     if (it.step_begin == 0) W.init(p, lab, id);
     else W = *st;
     dev::walk_range<true>(p, lab, W, it.step_begin, it.step_end, id, trig);
+    double* rec = p.wstate + w * (kDumpFixed + 3 * p.n_shapes);
     if (it.step_end == static_cast<uint32_t>(p.n_steps)) {
-        W.finish(p, p.wstate + w * (kDumpFixed + 3 * p.n_shapes));
+        W.finish(p, rec);
     } else {
         *st = W;
-        if (it.flags & kItemRecord) W.finish(p, p.wstate + w * (kDumpFixed + 3 * p.n_shapes));
+        if (it.flags & kItemRecord) W.finish(p, rec);
     }
 }
 
@@ -105,8 +108,8 @@ __global__ __launch_bounds__(kBlock) RMS_WALK_OCCUPANCY void walk_packed_kernel(
 __global__ __launch_bounds__(kBlock) void start_try_kernel(WalkPlan p) {
     const int64_t w = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
     if (w >= p.n_walkers) return;
-    const Ids id{static_cast<uint32_t>(w), static_cast<uint32_t>(w >> 32),
-                 static_cast<uint32_t>(p.seed), static_cast<uint32_t>(p.seed >> 32)};
+    const Ids id{static_cast<uint32_t>(w), 0u, static_cast<uint32_t>(p.seed),
+                 static_cast<uint32_t>(p.seed >> 32)};
     p.start_try[w] = dev::start_try_of(p, id);
 }
 
@@ -170,8 +173,8 @@ __global__ __launch_bounds__(kBlock) void order_keys_kernel(WalkPlan p, uint32_t
                                                             uint32_t* keys, int cb) {
     const int64_t w = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
     if (w >= p.n_walkers) return;
-    const Ids id{static_cast<uint32_t>(w), static_cast<uint32_t>(w >> 32),
-                 static_cast<uint32_t>(p.seed), static_cast<uint32_t>(p.seed >> 32)};
+    const Ids id{static_cast<uint32_t>(w), 0u, static_cast<uint32_t>(p.seed),
+                 static_cast<uint32_t>(p.seed >> 32)};
     const dev::Start st = dev::draw_start(p, id);
     const dev::Coords k = dev::coords_of(static_cast<uint32_t>(st.lin), static_cast<uint32_t>(p.nx),
                                          static_cast<uint32_t>(p.nx) * static_cast<uint32_t>(p.ny),
@@ -295,7 +298,7 @@ template <class Walker, typename LabelT>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(Walker::kWaves, 8))) void walk_seg_kernel(
     WalkPlan p, uint32_t n_seg, uint32_t seg_steps, uint32_t waves_per_queue,
     uint32_t poll_limit) {
-    __shared__ double trig[Walker::kTrig ? 2 * kTrigSize : 2];
+    __shared__ double2 trig[Walker::kTrig ? kTrigSize + 1 : 1];
     load_trig<Walker>(p, trig);  // the only block barrier, before the loop
     const LabelT* __restrict__ lab = static_cast<const LabelT*>(p.labels);
     Walker* st = static_cast<Walker*>(p.seg_state);
@@ -334,7 +337,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(Walker::
         const int64_t slot = static_cast<int64_t>(sw) * kWave + lane;
         const uint32_t w = p.order[slot];
         if (w != kNoWalker) {
-            const Ids id{w, 0u, static_cast<uint32_t>(p.seed), static_cast<uint32_t>(p.seed >> 32)};
+            const Ids id = dev::walker_ids<Walker>(w, p.seed);
             Walker W;
             if (seg == 0) W.init(p, lab, id);
             else W = st[slot];

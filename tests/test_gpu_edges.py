@@ -147,3 +147,20 @@ def test_mixed_form_edges(cells):
         if o["signal"].size:
             assert np.max(np.abs(g["signal"] - o["signal"])) <= 1e-3
         assert np.max(np.abs(g["dump"][same, 0:3] - o["dump"][same, 0:3])) <= 1e-5
+
+
+def test_walker_count_limit(cells):
+    """Walker indices are 32-bit (2^32 - 1 marks an empty thread slot): a run
+    of 2^32 - 1 walkers is refused before anything is allocated, and the next
+    run on the same substrate is unaffected."""
+    lab, D, kap, T2 = cells
+    print("[case] walker count limit", flush=True)
+    sub = rms.rms_create_substrate(lab, 0.1, D, kap, T2)
+    try:
+        with pytest.raises(rms.RmsError) as e:
+            rms.rms_run(sub, seed=1, n_walkers=2**32 - 1, n_steps=10, dt=2e-4)
+        assert e.value.code == -1 and "2^32 - 2" in str(e.value)
+        r = rms.rms_run(sub, seed=1, n_walkers=300, n_steps=10, dt=2e-4)
+        assert r["n_face_events"] > 0
+    finally:
+        sub.close()
