@@ -199,8 +199,10 @@ def _tissue(n_labels, kappa):
 
 
 def serve(args):
-    """Continuous-batching benchmark: Poisson arrivals at 0.7 of the measured
-    capacity; latency = completion - arrival."""
+    """Continuous-batching benchmark: capacity with the whole trace queued at
+    once, the plain form on the same trace (each request its own rms_run, one
+    after another), then Poisson arrivals at 0.7 of the capacity; latency =
+    completion - arrival."""
     import torch
     import paper_2012_06478_amd as rms
     assert torch.cuda.is_available(), "bench needs a GPU"
@@ -240,6 +242,15 @@ def serve(args):
         cap_busy = (c1["busy_s"] - c0["busy_s"]) / cap_el
         log(f"[serve] capacity {cap:.3e} walker-steps/s ({len(reqs)} requests queued at once, "
             f"{cap_el:.2f} s, device busy {cap_busy:.3f})")
+        # the plain form on the same trace: each request as its own rms_run, one
+        # after another (what a caller without the server would do)
+        t0 = time.perf_counter()
+        for q in reqs:
+            rms.rms_run(subs[q["sub"]], seed=q["seed"], n_walkers=q["n_walkers"],
+                        n_steps=q["n_steps"], dt=q["dt"], waveform=q["waveform"], dirs=q["dirs"],
+                        bvals=q["bvals"], precision=prec, params=_tissue(nl[q["sub"]], q["kappa"]))
+        plain = sum(q["n_walkers"] * q["n_steps"] for q in reqs) / (time.perf_counter() - t0)
+        log(f"[serve] plain rms_run, one request after another: {plain:.3e} walker-steps/s")
         work = np.array([q["n_walkers"] * q["n_steps"] for q in reqs], float)
         rate = args.serve_load * cap / work.mean()  # requests per second
         rng = np.random.default_rng(11)
@@ -288,6 +299,7 @@ def serve(args):
         "p50_queue_s": float(np.percentile(queue, 50)),
         "p99_queue_s": float(np.percentile(queue, 99)),
         "capacity_walker_steps_per_s": cap, "capacity_device_busy_frac": cap_busy,
+        "plain_sequential_walker_steps_per_s": plain,
         "offered_load": args.serve_load,
         "device_busy_frac": (st["busy_s"] - st0["busy_s"]) / (end - start),
         "launches": st["launches"] - st0["launches"],
