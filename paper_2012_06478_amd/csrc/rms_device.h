@@ -233,6 +233,29 @@ __host__ __device__ __forceinline__ void event_order(const Real g[3], const Real
     ax[2] = 3 - ax[0] - ax[1];
 }
 
+// m ? x : y for a word m of all ones or all zeros, as one three-input bit
+// operation per 32-bit half (truth table 0xE4 over the operand patterns 0xF0,
+// 0xCC, 0xAA).  gfx950 issues these two at a time from different waves,
+// where a select on a lane mask (a VOP3 instruction) issues alone; the end
+// point's selects use them with masks taken from the reflect and pass bits.
+__device__ __forceinline__ double select_bits(uint32_t m, double x, double y) {
+    const uint64_t xb = __double_as_longlong(x), yb = __double_as_longlong(y);
+    const uint32_t lo = __builtin_amdgcn_bitop3_b32(static_cast<uint32_t>(xb),
+                                                    static_cast<uint32_t>(yb), m, 0xE4);
+    const uint32_t hi = __builtin_amdgcn_bitop3_b32(static_cast<uint32_t>(xb >> 32),
+                                                    static_cast<uint32_t>(yb >> 32), m, 0xE4);
+    return __longlong_as_double(static_cast<long long>((static_cast<uint64_t>(hi) << 32) | lo));
+}
+
+__device__ __forceinline__ float select_bits(uint32_t m, float x, float y) {
+    return __uint_as_float(__builtin_amdgcn_bitop3_b32(__float_as_uint(x), __float_as_uint(y), m, 0xE4));
+}
+
+// all ones if bit a of w is set, else zero
+__device__ __forceinline__ uint32_t bit_mask(uint32_t w, int a) {
+    return static_cast<uint32_t>(static_cast<int32_t>(w << (31 - a)) >> 31);
+}
+
 // v[a] for a runtime axis index a in {0, 1, 2}, as two selects (the three
 // reads are unconditional so the compiler does not branch on a)
 template <typename T>
@@ -571,9 +594,14 @@ struct WalkerF64T {
         for (int a = 0; a < 3; ++a) {
             const bool pos = (posm >> a) & 1u;
             const double fr = fma(lend, v[a], o[a]);
-            const double t = (refl >> a) & 1u ? (pos ? 2.0 : 0.0) - fr : fr;
+            const double t = select_bits(bit_mask(refl, a), (pos ? 2.0 : 0.0) - fr, fr);
             d[a] += t - o[a];
-            const double shift = (passed >> a) & 1u ? (pos ? 1.0 : -1.0) : 0.0;
+            // +-1 after a pass, else 0: only the high word is not zero (the and
+            // as a three-input operation, truth table 0xC0, for the same reason)
+            const uint32_t one_hi = pos ? 0x3FF00000u : 0xBFF00000u;
+            const uint32_t shift_hi = __builtin_amdgcn_bitop3_b32(bit_mask(passed, a), one_hi, 0u, 0xC0);
+            const double shift =
+                __longlong_as_double(static_cast<long long>(static_cast<uint64_t>(shift_hi) << 32));
             o[a] = fmin(fmax(t - shift, 0.0), 1.0);
         }
         // phase: a zero gradient sample adds exactly nothing, so no test for it
@@ -795,10 +823,13 @@ struct WalkerMixedT {
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
             const bool pos = (posm >> a) & 1u;
-            const bool ps = (passed >> a) & 1u;
             const float fr = fmaf(lend, v[a], o[a]);
-            const float t = (refl >> a) & 1u ? (pos ? 2.0f : 0.0f) - fr : fr;
-            const float shift = ps ? (pos ? 1.0f : -1.0f) : 0.0f;
+            const float t = select_bits(bit_mask(refl, a), (pos ? 2.0f : 0.0f) - fr, fr);
+            // +-1 after a pass, else 0 (the and as a three-input operation,
+            // truth table 0xC0, as in select_bits)
+            const uint32_t one = pos ? 0x3F800000u : 0xBF800000u;
+            const float shift =
+                __uint_as_float(__builtin_amdgcn_bitop3_b32(bit_mask(passed, a), one, 0u, 0xC0));
             o[a] = fminf(fmaxf(t - shift, 0.0f), 1.0f);
             base[a] += static_cast<double>(shift);  // exact: whole voxels
         }
