@@ -45,6 +45,8 @@ OPS_PER_WALKER_STEP = {
 OPS_TOTAL = sum(OPS_PER_WALKER_STEP.values())
 # MI355X VALU issue peak: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz lane-operations/s
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+# MI355X HBM3E peak, GB/s
+HBM_PEAK_GBPS = 8000.0
 
 WORKLOADS = ("ellipsoids200", "cylinder32", "axons")
 
@@ -627,6 +629,8 @@ def main():
     value = ws * args.steps / el
     kernel_s = float(np.mean(kms)) / 1e3
     achieved = OPS_TOTAL * ws / kernel_s / 1e12
+    traffic = (traffic_from_profile(c["name"], args.precision)
+               if c["n_walkers"] == default_walkers and args.walk_kernel == "auto" else None)
     line = {
         "metric": "walker-steps/s",
         "value": value,
@@ -646,9 +650,11 @@ def main():
                    "precision": args.precision},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS,
                      "unit": "TOP/s", "frac": achieved / VALU_PEAK_TOPS,
-                     "traffic": (traffic_from_profile(c["name"], args.precision)
-                                 if c["n_walkers"] == default_walkers
-                                 and args.walk_kernel == "auto" else None),
+                     "traffic": traffic,
+                     # the same launch's HBM bytes over its time, against the HBM peak
+                     "hbm": (None if traffic is None else
+                             {"achieved": traffic / kernel_s / 1e9, "peak": HBM_PEAK_GBPS,
+                              "unit": "GB/s", "frac": traffic / kernel_s / 1e9 / HBM_PEAK_GBPS}),
                      "kernel": walk_kernel_name(prec == rms.RMS_FP64, c, r["walk_kernel"]),
                      "kernel_ms": kernel_s * 1e3, "ops_per_walker_step": OPS_TOTAL},
         "last_signal_b_max_dir0": [float(r["signal"][0, -1, 0].real),
