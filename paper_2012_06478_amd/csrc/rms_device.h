@@ -491,6 +491,13 @@ struct WalkerF64T {
         int nev = __builtin_popcount(evm);
         int ax[3];
         event_order(g, m, ax);
+        // each lane's byte steps in LDS, one row per axis, so that an event's
+        // step is read by its axis index instead of picked by two selects
+        __shared__ int32_t sst_lds[3][kBlock];
+        const uint32_t tid = threadIdx.x;
+        sst_lds[0][tid] = sst[0];
+        sst_lds[1][tid] = sst[1];
+        sst_lds[2][tid] = sst[2];
         // Offsets and entries of the voxels the events reach if every face
         // passes (the common case), loaded together so the step waits for
         // memory once rather than once per event.
@@ -500,7 +507,7 @@ struct WalkerF64T {
             uint32_t c = lb;
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
-                c += static_cast<uint32_t>(pick(sst, ax[k]));
+                c += static_cast<uint32_t>(sst_lds[ax[k]][tid]);
                 cpath[k] = c;
                 if (k < nev0) rsp[k] = entry(lab, c);
             }
@@ -529,7 +536,7 @@ struct WalkerF64T {
                     nbk = cpath[k];
                     raw = rsp[k];
                 } else {  // after a reflection, or a face a permeation brought in
-                    nbk = lb + static_cast<uint32_t>(pick(sst, a));
+                    nbk = lb + static_cast<uint32_t>(sst_lds[a][tid]);
                     raw = entry(lab, nbk);
                 }
                 const int nl = static_cast<int>(raw & LabelBits<LabelT>::kMask);
