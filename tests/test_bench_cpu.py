@@ -47,3 +47,12 @@ def test_traffic_needs_the_profiled_sources():
     assert len(sha) == 16 and int(sha, 16) >= 0
     t = bench.traffic_from_profile("axons400x400x1000_u16", "fp64")
     assert t is None or t > 0
+
+
+def test_committed_counters_match_the_walk_sources():
+    """The committed counter summaries of the default workload (both forms)
+    were taken on the current walk sources, so the bench line carries their
+    traffic; a change to the walk sources needs the counters taken again."""
+    for form in ("fp64", "mixed"):
+        t = bench.traffic_from_profile("axons400x400x1000_u16", form)
+        assert t is not None and t > 0, form
