@@ -607,8 +607,8 @@ def main():
     sub = rms.rms_create_substrate(c["labels"], c["voxel_um"], c["D"], c["kappa"], c["T2"],
                                    c.get("dead"))
     torch.cuda.synchronize()
-    log(f"[bench] substrate resident ({c['labels'].nbytes / 1e6:.1f} MB) in "
-        f"{time.perf_counter() - t0:.2f} s")
+    create_s = time.perf_counter() - t0
+    log(f"[bench] substrate resident ({c['labels'].nbytes / 1e6:.1f} MB) in {create_s:.2f} s")
     run = dict(seed=c["seed"], n_walkers=c["n_walkers"], n_steps=c["n_steps"], dt=c["dt"],
                waveform=c["waveform"], dirs=c["dirs"], bvals=c["bvals"], precision=prec,
                stream=stream)
@@ -657,6 +657,10 @@ def main():
                               "unit": "GB/s", "frac": traffic / kernel_s / 1e9 / HBM_PEAK_GBPS}),
                      "kernel": walk_kernel_name(prec == rms.RMS_FP64, c, r["walk_kernel"]),
                      "kernel_ms": kernel_s * 1e3, "ops_per_walker_step": OPS_TOTAL},
+        # the labels come from host memory: one run together with its substrate's
+        # creation (host padding, upload over PCIe) is the rate of a single job
+        "substrate_create_s": create_s,
+        "one_run_with_substrate_upload": ws / (create_s + el / args.steps),
         "last_signal_b_max_dir0": [float(r["signal"][0, -1, 0].real),
                                    float(r["signal"][0, -1, 0].imag)],
     }

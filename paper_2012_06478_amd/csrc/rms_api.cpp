@@ -6,10 +6,12 @@
 
 #include <algorithm>
 #include <chrono>
+#include <memory>
 #include <mutex>
 #include <cmath>
 #include <cstring>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "rms_host.h"
@@ -610,6 +612,89 @@ void fill_result(const RunSetup& r, const double* res, rms_result* out) {
     out->max_step_over_voxel = r.max_sigma;
 }
 
+namespace {
+
+// Host threads for the passes over a label volume (the 400x400x1000 volume
+// took about 0.5 s on one core): up to 16, one for small volumes.
+int volume_threads(int64_t nvox) {
+    if (nvox < (int64_t(1) << 22)) return 1;
+    const unsigned hc = std::thread::hardware_concurrency();
+    return hc == 0 ? 1 : static_cast<int>(std::min(hc, 16u));
+}
+
+// f(begin, end, t) over nt contiguous ranges of [0, n) on nt threads; ranges
+// whose thread could not be started run on the calling thread.
+template <class F>
+void parallel_ranges(int64_t n, int nt, const F& f) {
+    std::vector<std::thread> th;
+    int started = 1;
+    try {
+        th.reserve(static_cast<size_t>(nt));
+        for (int t = 1; t < nt; ++t) {
+            th.emplace_back(f, n * t / nt, n * (t + 1) / nt, t);
+            ++started;
+        }
+    } catch (...) {
+    }
+    f(int64_t(0), n / nt, 0);
+    for (int t = started; t < nt; ++t) f(n * t / nt, n * (t + 1) / nt, t);
+    for (auto& x : th) x.join();
+}
+
+// Voxels per label over [b, e); the index of the first voxel whose label is
+// out of range (or -1), and, with dead labels, the voxels a walker may start in.
+template <typename T>
+void scan_labels(const T* lab, int64_t b, int64_t e, int n_labels, const uint8_t* dead,
+                 int64_t* count, int64_t* first_bad, std::vector<uint32_t>* allowed) {
+    for (int64_t i = b; i < e; ++i) {
+        const uint32_t l = lab[i];
+        if (l >= static_cast<uint32_t>(n_labels)) {
+            *first_bad = i;
+            return;
+        }
+        ++count[l];
+        if (dead && !dead[l]) allowed->push_back(static_cast<uint32_t>(i));
+    }
+}
+
+// Padded planes [zb, ze) of the device volume: each entry the label of the
+// voxel it stands for (periodic wrap in the halo) with the halo flags of the
+// axes along which it lies outside the volume in the bits from `shift` up.
+template <typename Src, typename Dst>
+void pad_planes(const Src* lab, Dst* pad, int64_t nx, int64_t ny, int64_t nz, int shift,
+                int64_t zb, int64_t ze) {
+    const int64_t px = nx + 2, py = ny + 2, pz = nz + 2;
+    for (int64_t zp = zb; zp < ze; ++zp) {
+        const int64_t z = (zp + nz - 1) % nz;
+        const uint32_t fz = zp == 0 || zp == pz - 1 ? 4u : 0u;
+        for (int64_t yp = 0; yp < py; ++yp) {
+            const int64_t y = (yp + ny - 1) % ny;
+            const uint32_t f = fz | (yp == 0 || yp == py - 1 ? 2u : 0u);
+            const Src* src = lab + (z * ny + y) * nx;
+            Dst* dst = pad + (zp * py + yp) * px;
+            const uint32_t fi = f << shift, fh = (f | 1u) << shift;
+            for (int64_t x = 0; x < nx; ++x) dst[x + 1] = static_cast<Dst>(src[x] | fi);
+            dst[0] = static_cast<Dst>(src[nx - 1] | fh);
+            dst[nx + 1] = static_cast<Dst>(src[0] | fh);
+        }
+    }
+}
+
+template <typename Dst>
+void pad_volume(const void* labels, int label_bytes, Dst* pad, const int64_t dims[3], int shift,
+                int nt) {
+    parallel_ranges(dims[2] + 2, nt, [&](int64_t zb, int64_t ze, int) {
+        if (label_bytes == 1)
+            pad_planes(static_cast<const uint8_t*>(labels), pad, dims[0], dims[1], dims[2], shift,
+                       zb, ze);
+        else
+            pad_planes(static_cast<const uint16_t*>(labels), pad, dims[0], dims[1], dims[2],
+                       shift, zb, ze);
+    });
+}
+
+}  // namespace
+
 }  // namespace rms
 
 extern "C" {
@@ -655,21 +740,52 @@ int rms_create_substrate(const void* labels, int label_bytes, const int64_t dims
     if (dead)
         for (int l = 0; l < n_labels; ++l) sub->dead[l] = dead[l] ? 1 : 0;
 
-    // every label in range; list the voxels a walker may start in
+    // every label in range; list the voxels a walker may start in (per
+    // thread over contiguous ranges, joined in voxel order)
     std::vector<uint32_t> allowed;
     bool any_dead = false;
     for (int l = 0; l < n_labels; ++l) any_dead |= sub->dead[l] != 0;
     sub->label_count.assign(n_labels, 0);
-    for (int64_t i = 0; i < nvox; ++i) {
-        const int l = label_bytes == 1 ? static_cast<const uint8_t*>(labels)[i]
-                                       : static_cast<const uint16_t*>(labels)[i];
-        if (l < n_labels) ++sub->label_count[l];
-        if (l >= n_labels) {
-            delete sub;
-            return fail(RMS_E_LABEL_RANGE, "voxel " + std::to_string(i) + " has label " +
-                                               std::to_string(l) + " >= n_labels");
+    const int nt = rms::volume_threads(nvox);
+    std::vector<std::vector<int64_t>> counts;
+    std::vector<std::vector<uint32_t>> allowed_t;
+    std::vector<int64_t> first_bad;
+    std::vector<uint8_t> oom;
+    try {
+        counts.assign(nt, std::vector<int64_t>(n_labels, 0));
+        allowed_t.resize(nt);
+        first_bad.assign(nt, -1);
+        oom.assign(nt, 0);
+        rms::parallel_ranges(nvox, nt, [&](int64_t b, int64_t e, int t) {
+            const uint8_t* dl = any_dead ? sub->dead.data() : nullptr;
+            try {  // nothing may leave a thread's function
+                if (label_bytes == 1)
+                    rms::scan_labels(static_cast<const uint8_t*>(labels), b, e, n_labels, dl,
+                                     counts[t].data(), &first_bad[t], &allowed_t[t]);
+                else
+                    rms::scan_labels(static_cast<const uint16_t*>(labels), b, e, n_labels, dl,
+                                     counts[t].data(), &first_bad[t], &allowed_t[t]);
+            } catch (...) {
+                oom[t] = 1;
+            }
+        });
+        if (std::find(oom.begin(), oom.end(), uint8_t(1)) != oom.end()) throw std::bad_alloc();
+        for (int t = 0; t < nt; ++t) {
+            if (first_bad[t] >= 0) {  // the ranges are in voxel order: the first one found
+                const int64_t i = first_bad[t];
+                const int l = label_bytes == 1 ? static_cast<const uint8_t*>(labels)[i]
+                                               : static_cast<const uint16_t*>(labels)[i];
+                delete sub;
+                return fail(RMS_E_LABEL_RANGE, "voxel " + std::to_string(i) + " has label " +
+                                                   std::to_string(l) + " >= n_labels");
+            }
+            for (int l = 0; l < n_labels; ++l) sub->label_count[l] += counts[t][l];
+            allowed.insert(allowed.end(), allowed_t[t].begin(), allowed_t[t].end());
+            std::vector<uint32_t>().swap(allowed_t[t]);
         }
-        if (any_dead && !sub->dead[l]) allowed.push_back(static_cast<uint32_t>(i));
+    } catch (const std::bad_alloc&) {
+        delete sub;
+        return fail(RMS_E_OOM, "host allocation failed");
     }
     if (any_dead && allowed.empty()) {
         delete sub;
@@ -682,36 +798,20 @@ int rms_create_substrate(const void* labels, int label_bytes, const int64_t dims
     const int64_t nx = dims[0], ny = dims[1], nz = dims[2];
     const int64_t px = nx + 2, py = ny + 2, pz = nz + 2;
     const int shift = rms::halo_shift(sub->dev_label_bytes);
-    std::vector<uint16_t> pad16;
-    std::vector<uint8_t> pad8;
-    try {
-        if (sub->dev_label_bytes == 1) pad8.resize(static_cast<size_t>(px * py * pz));
-        else pad16.resize(static_cast<size_t>(px * py * pz));
-    } catch (const std::bad_alloc&) {
+    const size_t n_pad = static_cast<size_t>(px * py * pz);
+    std::unique_ptr<uint16_t[]> pad16;  // every entry is written below
+    std::unique_ptr<uint8_t[]> pad8;
+    if (sub->dev_label_bytes == 1) pad8.reset(new (std::nothrow) uint8_t[n_pad]);
+    else pad16.reset(new (std::nothrow) uint16_t[n_pad]);
+    if (!pad8 && !pad16) {
         delete sub;
         return fail(RMS_E_OOM, "host allocation failed");
     }
-    for (int64_t zp = 0; zp < pz; ++zp) {
-        const int64_t z = (zp + nz - 1) % nz;
-        const uint32_t fz = zp == 0 || zp == pz - 1 ? 4u : 0u;
-        for (int64_t yp = 0; yp < py; ++yp) {
-            const int64_t y = (yp + ny - 1) % ny;
-            const uint32_t fy = yp == 0 || yp == py - 1 ? 2u : 0u;
-            const int64_t row = (z * ny + y) * nx, prow = (zp * py + yp) * px;
-            for (int64_t xp = 0; xp < px; ++xp) {
-                const int64_t x = (xp + nx - 1) % nx;
-                const uint32_t f = fz | fy | (xp == 0 || xp == px - 1 ? 1u : 0u);
-                const uint32_t l = label_bytes == 1 ? static_cast<const uint8_t*>(labels)[row + x]
-                                                    : static_cast<const uint16_t*>(labels)[row + x];
-                const uint32_t v = l | (f << shift);
-                if (sub->dev_label_bytes == 1) pad8[prow + xp] = static_cast<uint8_t>(v);
-                else pad16[prow + xp] = static_cast<uint16_t>(v);
-            }
-        }
-    }
-    const size_t pad_bytes = static_cast<size_t>(px * py * pz) * sub->dev_label_bytes;
-    const void* pad_src = sub->dev_label_bytes == 1 ? static_cast<const void*>(pad8.data())
-                                                    : static_cast<const void*>(pad16.data());
+    if (sub->dev_label_bytes == 1) rms::pad_volume(labels, label_bytes, pad8.get(), dims, shift, nt);
+    else rms::pad_volume(labels, label_bytes, pad16.get(), dims, shift, nt);
+    const size_t pad_bytes = n_pad * sub->dev_label_bytes;
+    const void* pad_src = sub->dev_label_bytes == 1 ? static_cast<const void*>(pad8.get())
+                                                    : static_cast<const void*>(pad16.get());
 
     hipError_t e = hipGetDevice(&sub->device);
     if (e == hipSuccess) e = hipMalloc(&sub->d_labels, pad_bytes);

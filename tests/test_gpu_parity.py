@@ -115,6 +115,19 @@ def test_dead_space_and_odd_steps():
     _assert_summary(g, o, 1e-9)
 
 
+def test_dead_space_on_a_volume_scanned_by_several_threads():
+    """A volume above 2^22 voxels: the host lists the voxels a walker may
+    start in on several threads, over contiguous ranges joined in voxel order;
+    every start (an index into that list) equals the oracle's."""
+    lab = cylinder_z(200, radius_vox=60.0, nz=130)  # 5.2e6 voxels
+    dead = np.array([1, 0], np.uint8)
+    g, o = _both(lab, 0.1, np.array([2.0, 2.0]), None, None, dead, seed=11, n_walkers=4000,
+                 n_steps=64, dt=2e-4, dirs=six_dirs())
+    assert np.all(g["dump"][:, 11] == 1)
+    _assert_walkers(g, o, 1e-9)
+    _assert_summary(g, o, 1e-9)
+
+
 def test_uint8_labels_beyond_flag_room():
     """uint8 volume with 46 labels: more than the uint8 device entries leave
     room for next to the halo flags, so the device volume is widened to

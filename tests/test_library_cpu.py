@@ -235,3 +235,16 @@ def test_device_event_order(tmp_path):
     out = subprocess.run([str(exe)], capture_output=True, text=True, check=True,
                          timeout=120).stdout.split()
     assert out == ["0", "0", "0", "0"], out
+
+
+def test_label_range_names_the_first_bad_voxel_of_a_large_volume():
+    """Volumes of more than 2^22 voxels are scanned by several host threads
+    over contiguous ranges: the error still names the first bad voxel."""
+    lab = np.zeros((130, 200, 200), np.uint16)  # 5.2e6 voxels, z slowest
+    lab[120, 7, 9] = 900   # in a late range
+    lab[40, 3, 5] = 700    # the first one in voxel order
+    with pytest.raises(rms.RmsError) as e:
+        rms.rms_create_substrate(lab, 0.1, [2.0, 2.0])
+    assert e.value.code == -2
+    first = (40 * 200 + 3) * 200 + 5
+    assert f"voxel {first} has label 700" in rms.rms_last_error()
