@@ -603,6 +603,10 @@ def main():
     if args.walkers:
         c["n_walkers"] = args.walkers
     prec = rms.RMS_FP64 if args.precision == "fp64" else rms.RMS_MIXED
+    # the process's first device allocation sets up the device's memory (about
+    # 0.15 s, once): a tiny substrate takes it before the timed creation
+    rms.rms_create_substrate(np.zeros((2, 2, 2), np.uint8), c["voxel_um"], [2.0]).close()
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
     sub = rms.rms_create_substrate(c["labels"], c["voxel_um"], c["D"], c["kappa"], c["T2"],
                                    c.get("dead"))
