@@ -248,3 +248,28 @@ def test_label_range_names_the_first_bad_voxel_of_a_large_volume():
     assert e.value.code == -2
     first = (40 * 200 + 3) * 200 + 5
     assert f"voxel {first} has label 700" in rms.rms_last_error()
+
+
+@pytest.mark.parametrize("option,value,needle", [
+    (rms.RMS_OPT_WALK_KERNEL, 7, "RMS_OPT_WALK_KERNEL"),
+    (rms.RMS_OPT_SERVER_WALKERS, -1, "RMS_OPT_SERVER_WALKERS"),
+    (rms.RMS_OPT_SEG_POLL_LIMIT, -1, "RMS_OPT_SEG_POLL_LIMIT"),
+    (rms.RMS_OPT_SEG_POLL_LIMIT, 1 << 32, "RMS_OPT_SEG_POLL_LIMIT"),
+    (99, 0, "unknown option"),
+])
+def test_options_refuse_values_outside_their_range(option, value, needle):
+    """Launch and server options are checked on the host; a refused value
+    leaves the option as it was."""
+    with pytest.raises(rms.RmsError) as e:
+        rms.rms_set_option(option, value)
+    assert e.value.code == -1
+    assert needle in rms.rms_last_error()
+
+
+def test_options_accept_their_documented_values():
+    for v in (rms.RMS_WALK_ONE_LAUNCH, rms.RMS_WALK_PERSISTENT, rms.RMS_WALK_AUTO):
+        rms.rms_set_option(rms.RMS_OPT_WALK_KERNEL, v)
+    rms.rms_set_option(rms.RMS_OPT_SERVER_WALKERS, 123456)
+    rms.rms_set_option(rms.RMS_OPT_SERVER_WALKERS, 0)          # automatic again
+    rms.rms_set_option(rms.RMS_OPT_SEG_POLL_LIMIT, 0xFFFFFFFE)
+    rms.rms_set_option(rms.RMS_OPT_SEG_POLL_LIMIT, 1 << 20)    # the default
