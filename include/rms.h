@@ -224,8 +224,11 @@ int rms_set_option(int option, int64_t value);
  *   out         receives the handle.
  * The substrate lives on the HIP device current at the call, as the volume
  * inside a one-voxel periodic halo: (nx+2)(ny+2)(nz+2) entries of 1 byte
- * (uint8 labels with n_labels <= 32) or 2 bytes (otherwise).  Returns
- * RMS_E_OOM if host staging or device memory runs out. */
+ * (uint8 labels with n_labels <= 32) or 2 bytes (otherwise).  Volumes of
+ * more than 2^22 voxels are checked and padded on up to 16 host threads
+ * (joined before the call returns).  A label >= n_labels gives
+ * RMS_E_LABEL_RANGE naming the first such voxel; RMS_E_OOM if host staging
+ * or device memory runs out. */
 int rms_create_substrate(const void* labels, int label_bytes, const int64_t dims[3],
                          double voxel_um, int n_labels, const double* D, const double* kappa,
                          const double* T2, const uint8_t* dead, rms_substrate** out);
